@@ -1,0 +1,66 @@
+"""The oracle's pins are sensitive: each plausible slip planted in a copy of
+the oracle source (on the CPU, in a temporary directory) must make at least
+one pin of test_oracle_pins.py fail.
+
+The one slip no pin can see is the tie rule of rounding at exact half-pixel
+coordinates (round half to even vs half up): the paper only says "nearest",
+so that choice is listed as unpinned.
+"""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+MUTANTS = {
+    "warp_sign": ("float w = gf - rv;          // R1", "float w = gf + rv;          // R1"),
+    "beta_sign": ("if (dw < zeta && dv > beta) ++O;", "if (dw < zeta && -dv < beta) ++O;"),
+    "zeta_non_strict": ("if (dw < zeta && dv > beta) ++O;", "if (dw <= zeta && dv > beta) ++O;"),
+    "ties_descending": ("return a.W < b.W; });", "return a.W < b.W || (a.W == b.W && a.g > b.g); });"),
+    "ex_backward": ("return (x + 1 < W) ? (D[(size_t)y * W + x + 1] - D[(size_t)y * W + x]) : 0.0f;",
+                    "return (x >= 1) ? (D[(size_t)y * W + x] - D[(size_t)y * W + x - 1]) : 0.0f;"),
+    "ey_sign": ("return (y + 1 < H) ? (D[(size_t)(y + 1) * W + x] - D[(size_t)y * W + x]) : 0.0f;",
+                "return (y + 1 < H) ? (D[(size_t)y * W + x] - D[(size_t)(y + 1) * W + x]) : 0.0f;"),
+    "cos_sin_swapped_in_dot": ("float a = ex * c;\n    float b = ey * s;", "float a = ex * s;\n    float b = ey * c;"),
+    "edge_threshold_non_strict": ("return (E > gamma) && (dot > 0.0f);", "return (E >= gamma) && (dot > 0.0f);"),
+    "angle_test_non_strict": ("return (E > gamma) && (dot > 0.0f);", "return (E > gamma) && (dot >= 0.0f);"),
+    "no_sqrt": ("return std::sqrt(q);", "return q;"),
+    "neighbours_floor": ("int ns = (N + 1) / 2;  // ceil(N/2)", "int ns = N / 2;"),
+    "half_length_rounded_up": ("const int h = scan_len[v] / 2;", "const int h = (scan_len[v] + 1) / 2;"),
+    "clamp_instead_of_drop": ("if (ix < 0 || ix >= W || iy < 0 || iy >= H) continue;  // R5: dropped",
+                              "ix = ix < 0 ? 0 : (ix >= W ? W - 1 : ix); iy = iy < 0 ? 0 : (iy >= H ? H - 1 : iy);"),
+    "truncate_coordinate": ("int ix = (int)std::rint(px);", "int ix = (int)std::floor(px);"),
+    "ratio_dropped": ("float rv = r * sm.V;\n        float w = gf - rv;          // R1",
+                      "float rv = sm.V;\n        float w = gf - rv;          // R1"),
+    "V_index_transposed": ("sm.V = D[(size_t)iy * W + ix];", "sm.V = D[((size_t)ix * W + iy) % ((size_t)H * W)];"),
+    "direction_cos_sin_swapped": ("cb = (float)std::cos(b * deg);\n        sb = (float)std::sin(b * deg);",
+                                  "sb = (float)std::cos(b * deg);\n        cb = (float)std::sin(b * deg);"),
+    "successor_only": ("for (int d = -ns; d <= ns; ++d) {\n            if (d == 0) continue;\n            int j = k + d;\n            if (j < 0 || j >= n) continue;\n            float dw = std::fabs(smp[k].W - smp[j].W);\n            float dv = smp[j].V - smp[k].V;\n            if (dw < zeta && dv > beta) ++O;",
+                       "for (int d = 1; d <= ns; ++d) {\n            int j = k + d;\n            if (j < 0 || j >= n) continue;\n            float dw = std::fabs(smp[k].W - smp[j].W);\n            float dv = smp[j].V - smp[k].V;\n            if (dw < zeta && dv > beta) ++O;"),
+    "mask_written_at_candidate": ("if (hit[k]) Mv[(size_t)smp[k].iy * W + smp[k].ix] = 1;",
+                                  "if (hit[k]) Mv[(size_t)y * W + x] = 1;"),
+}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(os.path.join(ROOT, "oracle", "occl_ref.cpp")).read()
+    assert src.count(old) >= 1, f"mutation site for {name} not found"
+    ign = shutil.ignore_patterns("*.so", "__pycache__", "*.tmp")
+    shutil.copytree(os.path.join(ROOT, "oracle"), tmp_path / "oracle", ignore=ign)
+    shutil.copytree(os.path.join(ROOT, "paper_2408_14050_amd"), tmp_path / "paper_2408_14050_amd",
+                    ignore=shutil.ignore_patterns("*.so", "__pycache__", "csrc", "*.tmp"))
+    os.makedirs(tmp_path / "tests")
+    for f in ("conftest.py", "test_oracle_pins.py"):
+        shutil.copy(os.path.join(ROOT, "tests", f), tmp_path / "tests" / f)
+    shutil.copytree(os.path.join(ROOT, "tests", "golden"), tmp_path / "tests" / "golden")
+    (tmp_path / "oracle" / "occl_ref.cpp").write_text(src.replace(old, new))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        "tests/test_oracle_pins.py"], cwd=tmp_path, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode != 0, f"mutant {name} survived every pin:\n{r.stdout[-2000:]}"
