@@ -1,0 +1,174 @@
+/*
+ * occl.h -- C ABI of the MI355X (gfx950) fast edge-aware occlusion detector.
+ *
+ * Method: Sippel, Seiler, Kaup, "Fast Edge-Aware Occlusion Detection in the
+ * Context of Multispectral Camera Arrays", ICIP 2024, Sec. 3, Eqs. (1)-(6).
+ * From the fused centre-view disparity map D the library computes the edge
+ * maps (Eq. 1), keeps the edge candidates that face each peripheral camera
+ * (Eq. 2), samples a scanline of 2*floor(L/2)+1 pixels along the camera's
+ * baseline through every candidate (Eq. 4), warps the samples into the
+ * peripheral view (W = g - r*V), sorts them, compares each sorted sample
+ * with its sorted neighbours (Eq. 5) and sets the occluded pixels of the
+ * per-view mask M (Eq. 6).
+ *
+ * Conventions (the readings of the paper the library implements):
+ *  - D is fp32, row-major [H][W], x to the right, y down.
+ *  - A view is given by the angle (degrees, double) of the baseline from the
+ *    centre camera to the peripheral camera, measured from +x towards +y,
+ *    and the baseline ratio r > 0 (disparity in that view = r * D).
+ *  - The direction vector (cos, sin) of an angle is computed on the host in
+ *    double for the octant reference angle in (0, 45] degrees and rounded to
+ *    fp32; multiples of 90 degrees are exact.
+ *  - E_x, E_y are forward differences, zero on the last column / row;
+ *    a pixel is a candidate iff sqrt(E_x^2 + E_y^2) > gamma and
+ *    E_x*cos + E_y*sin > 0 (fp32, no fused multiply-add).
+ *  - Scanline coordinates: fp32 multiply then add, round half to even;
+ *    samples outside the frame are dropped.
+ *  - Sort ascending by W, ties by ascending offset g; a sorted sample k is
+ *    occluded iff for some d in +-1..+-max(1, ceil(N/2)):
+ *    |W_k - W_{k+d}| < zeta and V_{k+d} - V_k > beta.
+ *  - M[v][y][x] in {0, 1}, view-major, 1 = occluded in view v.
+ *
+ * Memory: D and M are device pointers owned by the caller; the library
+ * never allocates or frees them and only reads D / writes M on the
+ * context's stream.  They must stay valid until that stream's work is done.
+ * Every call is asynchronous on the context's stream unless stated.
+ *
+ * Errors: every function returns an occl_status.  Argument validation runs
+ * before anything is enqueued; a rejected call has no side effects.
+ * Asynchronous device faults surface at the next call or at occl_sync.  A
+ * context is not thread-safe: use one context per stream.
+ */
+#ifndef OCCL_H
+#define OCCL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct occl_ctx occl_ctx;
+
+typedef enum {
+    OCCL_OK = 0,
+    OCCL_ERR_INVALID_ARG = -1,   /* bad pointer, size, angle, ratio, threshold ... */
+    OCCL_ERR_OUT_OF_MEMORY = -2, /* workspace allocation failed or exceeds the cap */
+    OCCL_ERR_HIP = -3,           /* a HIP runtime call failed (message: occl_last_error) */
+    OCCL_ERR_UNSUPPORTED = -4,   /* e.g. resolved scan length L > OCCL_MAX_SCAN_LEN */
+    OCCL_ERR_NO_MODEL = -5,      /* the learned tile proposal was requested without weights */
+    OCCL_ERR_STATE = -6          /* call not valid in the context's current state */
+} occl_status;
+
+#define OCCL_MAX_VIEWS 64
+#define OCCL_MAX_SCAN_LEN 1023
+#define OCCL_MAX_NEIGHBOURS 64
+
+/* flags of occl_params */
+#define OCCL_FLAG_SYNC 1u            /* synchronise the stream before returning */
+#define OCCL_FLAG_VALIDATE_INPUT 2u  /* check D for non-finite values first (synchronises) */
+#define OCCL_FLAG_USE_CNN 4u         /* learned tile proposal + exact fallback (needs weights) */
+
+/* Detector parameters (Sec. 3: gamma of Eq. 2, zeta and beta of Eq. 5,
+ * N of Eq. 5, L of Eqs. 3-4). */
+typedef struct {
+    uint32_t struct_size;        /* must be sizeof(occl_params) */
+    float edge_thr;              /* gamma, px (> 0 is usual; any finite value accepted) */
+    float disp_thr;              /* beta, px, finite */
+    float dist_thr;              /* zeta, px, finite */
+    int32_t neighbours;          /* N, 1..OCCL_MAX_NEIGHBOURS */
+    int32_t scan_len;            /* L > 0: the same L for every view;
+                                    0: per view L = ceil(max(D) * r) + 2 (fp32 product);
+                                   -1: per view L = ceil(2 * r * (max(D) - min(D))) (Eq. 3
+                                       with the ratio).  0 and -1 read max/min of D back
+                                       to the host, so the call synchronises. */
+    const int32_t* scan_len_per_view; /* optional host array [n_views]; overrides scan_len */
+    uint32_t flags;              /* OCCL_FLAG_* */
+    float cnn_lo, cnn_hi;        /* tile-probability band that falls back to the exact path */
+} occl_params;
+
+/* Fills *p with the defaults gamma = 1, beta = 0.5, zeta = 1, N = 1, L = 0,
+ * no flags, band [0.05, 0.95]. */
+void occl_params_default(occl_params* p);
+
+/* Creates a context on HIP device `device`.  `hip_stream` is the hipStream_t
+ * every call of this context is enqueued on (NULL: the device's default
+ * stream).  The library never creates or destroys streams.  The hints size
+ * the initial workspace (0: grow on first use). */
+occl_status occl_init(occl_ctx** out, int device, void* hip_stream, size_t max_pixels_hint,
+                      int32_t max_views_hint);
+
+/* One frame, n_views views.
+ *   D          device fp32 [H][W], row-major contiguous (16-byte alignment and W % 4 == 0
+ *              select the vectorised path; anything else is still correct)
+ *   H, W       >= 0; H*W == 0 or n_views == 0 is a valid empty call (nothing enqueued)
+ *   n_views    0..OCCL_MAX_VIEWS
+ *   angles_deg host double [n_views], finite
+ *   ratios     host float [n_views], finite and > 0
+ *   params     host occl_params
+ *   M          device uint8 [n_views][H][W]; every byte is written with 0 or 1 */
+occl_status occl_detect(occl_ctx* ctx, const float* D, int32_t H, int32_t W, int32_t n_views,
+                        const double* angles_deg, const float* ratios, const occl_params* params,
+                        uint8_t* M);
+
+/* A frame of a batch: its own size, mask and optionally its own scan lengths
+ * (host array [n_views]; NULL: params->scan_len / scan_len_per_view). */
+typedef struct {
+    const float* D;
+    int32_t H, W;
+    uint8_t* M;
+    const int32_t* scan_len_per_view;
+} occl_frame;
+
+/* Many frames of uneven size with the same views, in one graph launch on
+ * the context's stream.  The launch shape is taken from the autotuner
+ * cache.  Per-frame semantics are exactly those of occl_detect. */
+occl_status occl_detect_batched(occl_ctx* ctx, int32_t n_frames, const occl_frame* frames,
+                                int32_t n_views, const double* angles_deg, const float* ratios,
+                                const occl_params* params);
+
+/* Candidates per view of the most recent occl_detect (host int64 [n_views]);
+ * synchronises the stream. */
+occl_status occl_last_candidate_counts(occl_ctx* ctx, int64_t* out, int32_t n_views);
+
+/* Edge magnitude E and angle A = atan2(E_y, E_x) of Eq. (1) (device fp32 [H][W] each;
+ * either may be NULL). */
+occl_status occl_edges(occl_ctx* ctx, const float* D, int32_t H, int32_t W, float* E, float* A);
+
+/* Confusion counts of two masks (Eq. 7 inputs): pred, ref device uint8 [n];
+ * out host uint64[4] = {TP, FP, FN, TN}; synchronises the stream. */
+occl_status occl_confusion(occl_ctx* ctx, const uint8_t* pred, const uint8_t* ref, int64_t n,
+                           uint64_t* out);
+
+/* Waits for the context's stream; reports a pending device error. */
+occl_status occl_sync(occl_ctx* ctx);
+
+/* Synchronises, frees every context-owned resource and the context. NULL is a no-op. */
+occl_status occl_release(occl_ctx* ctx);
+
+/* Stage timing with HIP events recorded on the context's stream around each
+ * stage of every subsequent call (for benchmarks; adds event records
+ * between launches).  Enabling resets the accumulators.
+ * occl_profile_read synchronises and returns, per stage, the summed
+ * milliseconds and the number of launches timed since the last enable. */
+#define OCCL_STAGE_EDGES 0      /* k_edges_candidates: Eqs. (1)-(2) + mask clear */
+#define OCCL_STAGE_SCANLINES 1  /* k_scanlines: Eqs. (4)-(6) */
+#define OCCL_STAGE_CNN 2        /* learned tile proposal (pack, convolutions, routing) */
+#define OCCL_STAGE_FALLBACK 3   /* exact fallback on uncertain tiles */
+#define OCCL_N_STAGES 4
+occl_status occl_profile_enable(occl_ctx* ctx, int32_t enable);
+occl_status occl_profile_read(occl_ctx* ctx, double* ms /* [OCCL_N_STAGES] */,
+                              int64_t* launches /* [OCCL_N_STAGES] */);
+
+const char* occl_status_string(occl_status s);
+const char* occl_last_error(const occl_ctx* ctx);
+
+/* The direction vector the library uses for a baseline angle (host only). */
+occl_status occl_direction(double angle_deg, float* c, float* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OCCL_H */

@@ -399,6 +399,48 @@ int occl_ref_detect(const float* D, int H, int W, int n_views, const double* ang
     return 0;
 }
 
+/* The same detector restricted to a window [x0, x1) x [y0, y1) of the mask:
+ * every candidate whose scanline can reach the window (it lies within
+ * floor(L/2) + 1 pixels of it) is processed exactly as in occl_ref_detect and
+ * only hits inside the window are written to Mw [n_views][y1-y0][x1-x0].
+ * Lets large frames be checked on sampled windows. */
+int occl_ref_detect_window(const float* D, int H, int W, int n_views, const double* angles,
+                           const float* ratios, const int* scan_len, float gamma, float beta,
+                           float zeta, int neighbours, int x0, int y0, int x1, int y1,
+                           unsigned char* Mw) {
+    if (!D || !angles || !ratios || !scan_len || !Mw || H < 1 || W < 1 || n_views < 1 ||
+        neighbours < 1 || x0 < 0 || y0 < 0 || x1 > W || y1 > H || x0 >= x1 || y0 >= y1)
+        return -1;
+    const int ww = x1 - x0, wh = y1 - y0;
+    const int ns = neighbours_per_side(neighbours);
+    std::memset(Mw, 0, (size_t)ww * wh * n_views);
+    std::vector<Sample> smp;
+    std::vector<unsigned char> hit;
+    for (int v = 0; v < n_views; ++v) {
+        if (scan_len[v] < 1 || !(ratios[v] > 0.0f)) return -1;
+        float c, s;
+        ref_direction(angles[v], &c, &s);
+        const float r = ratios[v];
+        const int h = scan_len[v] / 2;
+        unsigned char* Mv = Mw + (size_t)ww * wh * v;
+        const int ya = std::max(0, y0 - h - 1), yb = std::min(H, y1 + h + 1);
+        const int xa = std::max(0, x0 - h - 1), xb = std::min(W, x1 + h + 1);
+        for (int y = ya; y < yb; ++y)
+            for (int x = xa; x < xb; ++x) {
+                float ex = edge_x(D, H, W, x, y), ey = edge_y(D, H, W, x, y);
+                if (!is_candidate(edge_mag(ex, ey), edge_dot(ex, ey, c, s), gamma)) continue;
+                build_scanline(D, H, W, x, y, c, s, r, h, smp);
+                sort_and_test(smp, zeta, beta, ns, hit);
+                for (size_t k = 0; k < smp.size(); ++k) {
+                    const Sample& sm = smp[k];
+                    if (hit[k] && sm.ix >= x0 && sm.ix < x1 && sm.iy >= y0 && sm.iy < y1)
+                        Mv[(size_t)(sm.iy - y0) * ww + (sm.ix - x0)] = 1;
+                }
+            }
+    }
+    return 0;
+}
+
 /* Occlusion-mask quality counts (Eq. (7) inputs): pred vs ref over n bytes.
  * out[0] = TP, out[1] = FP, out[2] = FN, out[3] = TN. */
 int occl_ref_confusion(const unsigned char* pred, const unsigned char* ref, long long n,

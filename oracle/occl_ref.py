@@ -39,6 +39,10 @@ def lib():
         L.occl_ref_confusion.argtypes = [u8, u8, C.c_longlong, i64]
         L.occl_ref_scanline_pixels.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
                                                C.c_int, i32, i32, C.c_int]
+        L.occl_ref_detect_window.argtypes = [fp, C.c_int, C.c_int, C.c_int, dp, fp, i32, C.c_float,
+                                             C.c_float, C.c_float, C.c_int, C.c_int, C.c_int,
+                                             C.c_int, C.c_int, u8]
+        L.occl_ref_detect_window.restype = C.c_int
         for f in ("occl_ref_direction", "occl_ref_edges", "occl_ref_candidates", "occl_ref_line",
                   "occl_ref_scan_len", "occl_ref_detect", "occl_ref_confusion",
                   "occl_ref_scanline_pixels"):
@@ -141,6 +145,24 @@ def detect(D, angles, ratios, scan_len, edge_thr=1.0, disp_thr=0.5, dist_thr=1.0
     if rc != 0:
         raise ValueError("invalid argument to occl_ref_detect")
     return M, T, nc
+
+
+def detect_window(D, angles, ratios, scan_len, x0, y0, x1, y1, edge_thr=1.0, disp_thr=0.5,
+                  dist_thr=1.0, neighbours=1):
+    """Mask of the window [y0:y1, x0:x1] only, shape [V, y1-y0, x1-x0]."""
+    D = _f32(D)
+    H, W = D.shape
+    a = np.ascontiguousarray(np.atleast_1d(angles), dtype=np.float64)
+    r = _f32(np.atleast_1d(ratios))
+    Ls = np.ascontiguousarray(np.broadcast_to(np.atleast_1d(scan_len), a.shape), dtype=np.int32)
+    Mw = np.empty((a.shape[0], y1 - y0, x1 - x0), np.uint8)
+    rc = lib().occl_ref_detect_window(_p(D, C.c_float), H, W, a.shape[0], _p(a, C.c_double),
+                                      _p(r, C.c_float), _p(Ls, C.c_int), float(edge_thr),
+                                      float(disp_thr), float(dist_thr), int(neighbours), int(x0),
+                                      int(y0), int(x1), int(y1), _p(Mw, C.c_ubyte))
+    if rc != 0:
+        raise ValueError("invalid argument to occl_ref_detect_window")
+    return Mw
 
 
 def detect_scene(sc, want_tight=False):

@@ -1,0 +1,653 @@
+// k_exact.hip -- gfx950 kernels of the exact detector (Sec. 3, Eqs. 1-6).
+//
+// Two launches per frame (plus one per extra register class of long scans):
+//   k_edges_candidates  dense, HBM-bound pass over D (Eqs. 1-2).  One wavefront
+//                       per 256-pixel row segment, 4 consecutive pixels per
+//                       lane (one float4 of row y and one of row y+1).  The
+//                       candidates of every view are compacted with ballots
+//                       and appended to that view's global list with a single
+//                       atomic per wavefront.  The same pass writes the zero
+//                       background of every mask, so each mask byte costs
+//                       one streaming write.  Its last block turns the
+//                       segment counters into a prefix for the next launch
+//                       and clears them for the next frame.
+//   k_scanlines<KMAX>   one wavefront per candidate scanline (Eqs. 4-6), the
+//                       (view, candidate) pairs handed out flat and
+//                       round-robin, so long and short lists balance.  A
+//                       scanline of n <= 64*K samples holds K samples per lane.
+//                       Sorting by (W, g): if W never descends along g the
+//                       samples are already in sorted order; with exactly one
+//                       descent the two ascending runs are merged by one
+//                       bitonic merge (the second run reversed); otherwise a
+//                       full bitonic sort.  Compare-exchange partners are
+//                       reached with DPP and permlane swaps (no LDS round
+//                       trip).  The sorted W and V go through LDS for the
+//                       neighbour test of Eq. (5); hits are byte stores of 1
+//                       into the cleared mask, so concurrent scanlines need
+//                       no atomics and the result does not depend on order.
+//
+// Every fp32 operation that feeds a decision is an explicitly rounded
+// intrinsic (__fmul_rn, __fadd_rn, __fsub_rn) and the library is built with
+// -ffp-contract=off: no product is ever fused into an add.
+#include "occl_internal.h"
+
+namespace occl {
+namespace {
+
+// ---------------------------------------------------------------------------
+// cross-lane helpers
+// ---------------------------------------------------------------------------
+#define OCCL_DPP(v, ctrl) ((uint32_t)__builtin_amdgcn_mov_dpp((int)(v), (ctrl), 0xF, 0xF, false))
+
+// Value of lane (lane ^ m) for m in {1, 2, 4, 8, 16, 32}.
+//   1, 2  quad permutations
+//   4     row_half_mirror then quad reverse:  7 - (i ^ 3) = i ^ 4 within 8
+//   8     row_mirror then row_half_mirror:   15 - (i ^ 7) = i ^ 8 within 16
+//   16    permlane16_swap (odd rows of one copy <-> even rows of the other)
+//   32    permlane32_swap (upper half of one copy <-> lower half of the other)
+__device__ __forceinline__ uint32_t xchg(uint32_t v, int m, int lane) {
+    switch (m) {
+        case 1: return OCCL_DPP(v, 0xB1);
+        case 2: return OCCL_DPP(v, 0x4E);
+        case 4: return OCCL_DPP(OCCL_DPP(v, 0x141), 0x1B);
+        case 8: return OCCL_DPP(OCCL_DPP(v, 0x140), 0x141);
+        case 16: {
+            const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+            return (lane & 16) ? (uint32_t)p[0] : (uint32_t)p[1];
+        }
+        default: {
+            const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+            return (lane & 32) ? (uint32_t)p[0] : (uint32_t)p[1];
+        }
+    }
+}
+
+__device__ __forceinline__ uint64_t xchg64(uint64_t v, int m, int lane) {
+    const uint32_t lo = xchg((uint32_t)v, m, lane);
+    const uint32_t hi = xchg((uint32_t)(v >> 32), m, lane);
+    return ((uint64_t)hi << 32) | (uint64_t)lo;
+}
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// LDS exchange inside one wavefront: keeps the compiler from moving LDS
+// accesses across this point (one wavefront's LDS operations are processed
+// in order by the hardware).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// fp32 <-> totally ordered uint32 (ascending float order = ascending uint order)
+__device__ __forceinline__ uint32_t f2ord(float w) {
+    uint32_t u = __float_as_uint(w);
+    if (u == 0x80000000u) u = 0u;  // -0 sorts as +0
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float ord2f(uint32_t o) {
+    const uint32_t u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+    return __uint_as_float(u);
+}
+
+// ---------------------------------------------------------------------------
+// Eq. (1) + Eq. (2): edges, candidates, mask clear
+// ---------------------------------------------------------------------------
+// Exclusive prefix of the segment counters, computed once per frame by the
+// last block of the edge pass, which also clears the counters and the block
+// counter for the next frame (so no separate clearing launch is needed and
+// the sequence can be replayed from a captured graph).  `prefix` gets
+// nseg + 1 entries.
+__device__ void finish_segments(int32_t* __restrict__ counts, int32_t* __restrict__ prefix,
+                                int nseg) {
+    __shared__ int wsum[kEdgeThreads / 64];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    constexpr int PER = (kMaxSegments + kEdgeThreads - 1) / kEdgeThreads;
+    int c[PER];
+    int sum = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int sg = t * PER + j;
+        c[j] = (sg < nseg) ? __hip_atomic_load(&counts[sg * kCounterPad], __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT)
+                           : 0;
+        sum += c[j];
+    }
+    // inclusive scan of the per-thread sums: within the wavefront, then across
+    int x = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    int wbase = 0;
+    for (int w = 0; w < wave; ++w) wbase += wsum[w];
+    int run = wbase + x - sum;  // exclusive prefix of this thread's first segment
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int sg = t * PER + j;
+        if (sg < nseg) {
+            prefix[sg] = run;
+            __hip_atomic_store(&counts[sg * kCounterPad], 0, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        run += c[j];
+    }
+    if (t == kEdgeThreads - 1) prefix[nseg] = run;
+}
+
+// E > gamma is decided without a square root: q = E_x^2 + E_y^2 (fp32, same
+// rounding as the definition) is compared with q_min, the smallest fp32 q
+// whose correctly rounded square root exceeds gamma (computed on the host).
+// This is exactly sqrt_rn(q) > gamma, since sqrt_rn is monotone.
+__global__ __launch_bounds__(kEdgeThreads) void k_edges_candidates(
+    const float* __restrict__ D, int H, int W, uint8_t* __restrict__ M, int n_views, ViewTable vt,
+    float q_min, ListLayout ll, uint32_t* __restrict__ lists, int32_t* __restrict__ counts,
+    int32_t* __restrict__ prefix, int vec) {
+    const int lane = threadIdx.x & 63;
+    const int y = blockIdx.y * kEdgeRows + (threadIdx.x >> 6);
+    const int x0 = blockIdx.x * kEdgeCols + lane * 4;
+    const bool row_ok = (y < H);
+    const bool live = row_ok && x0 < W;
+    if (row_ok) {
+        const float* row = D + (size_t)y * W;
+        const bool next_row = (y + 1 < H);
+        float d0[4] = {0.f, 0.f, 0.f, 0.f}, d1[4] = {0.f, 0.f, 0.f, 0.f};
+        float dn = 0.0f;
+        if (live) {
+            if (vec) {  // W % 4 == 0 and D 16-byte aligned, so x0 + 3 < W
+                const float4 a = *reinterpret_cast<const float4*>(row + x0);
+                d0[0] = a.x; d0[1] = a.y; d0[2] = a.z; d0[3] = a.w;
+                if (next_row) {
+                    const float4 b = *reinterpret_cast<const float4*>(row + W + x0);
+                    d1[0] = b.x; d1[1] = b.y; d1[2] = b.z; d1[3] = b.w;
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const bool in = (x0 + j < W);
+                    d0[j] = in ? row[x0 + j] : 0.0f;
+                    d1[j] = (in && next_row) ? row[W + x0 + j] : 0.0f;
+                }
+            }
+            dn = (x0 + 4 < W) ? row[x0 + 4] : 0.0f;
+        }
+        float ex[4], ey[4];
+        bool strong[4];
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int x = x0 + j;
+            const float right = (j < 3) ? d0[j + 1] : dn;
+            ex[j] = (x + 1 < W) ? __fsub_rn(right, d0[j]) : 0.0f;
+            ey[j] = next_row ? __fsub_rn(d1[j], d0[j]) : 0.0f;
+            const float q = __fadd_rn(__fmul_rn(ex[j], ex[j]), __fmul_rn(ey[j], ey[j]));
+            strong[j] = live && (x < W) && (q >= q_min);
+            any |= strong[j];
+        }
+        if (__ballot(any)) {
+            const int seg0 = (int)blockIdx.y / ll.block_rows_per_copy;
+            for (int v = 0; v < n_views; ++v) {
+                const float c = vt.c[v], s = vt.s[v];
+                uint64_t b[4];
+                int m4 = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float dot = __fadd_rn(__fmul_rn(ex[j], c), __fmul_rn(ey[j], s));
+                    const bool cand = strong[j] && (dot > 0.0f);
+                    m4 |= cand ? (1 << j) : 0;
+                    b[j] = __ballot(cand);
+                }
+                const int tot = __popcll(b[0]) + __popcll(b[1]) + __popcll(b[2]) + __popcll(b[3]);
+                if (tot == 0) continue;
+                int off = (int)(lanes_below(b[0]) + lanes_below(b[1]) + lanes_below(b[2]) +
+                                lanes_below(b[3]));
+                const int seg = v * ll.copies + seg0;
+                int base = 0;
+                if (lane == 0) base = atomicAdd(&counts[seg * kCounterPad], tot);
+                base = __builtin_amdgcn_readlane(base, 0);
+                uint32_t* dst = lists + (size_t)seg * ll.cap + base + off;
+                const uint32_t pix = (uint32_t)y * (uint32_t)W + (uint32_t)x0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (m4 & (1 << j)) *dst++ = pix + j;
+            }
+        }
+        if (live) {
+            const size_t HW = (size_t)H * W;
+            for (int v = 0; v < n_views; ++v) {
+                uint8_t* mrow = M + v * HW + (size_t)y * W;
+                if (vec) {
+                    *reinterpret_cast<uint32_t*>(mrow + x0) = 0u;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (x0 + j < W) mrow[x0 + j] = 0;
+                }
+            }
+        }
+    }
+    // The last block to finish turns the counters into the frame's prefix.
+    // No fence is needed: every segment atomic of this block has returned
+    // (its result addressed the list stores) before the completion atomic,
+    // device-scope atomics are performed at the coherence point, the last
+    // block reads the counters with atomic loads, and the list entries are
+    // only read by the next launch.
+    // Completion is counted in two levels (kDoneGroups group counters, then
+    // one top counter) so no single address takes one atomic per block.
+    __shared__ int s_last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned* done = reinterpret_cast<unsigned*>(counts + kMaxSegments * kCounterPad);
+        const unsigned ny = gridDim.y;
+        const unsigned grp = blockIdx.y % kDoneGroups;
+        const unsigned groups = ny < (unsigned)kDoneGroups ? ny : (unsigned)kDoneGroups;
+        const unsigned in_grp = gridDim.x * ((ny - grp + kDoneGroups - 1) / kDoneGroups);
+        int last = 0;
+        if (atomicAdd(&done[(1 + grp) * kCounterPad], 1u) == in_grp - 1)
+            last = (atomicAdd(&done[0], 1u) == groups - 1) ? 1 : 0;
+        s_last = last;
+    }
+    __syncthreads();
+    if (s_last) {
+        finish_segments(counts, prefix, n_views * ll.copies);
+        unsigned* done = reinterpret_cast<unsigned*>(counts + kMaxSegments * kCounterPad);
+        for (int i = threadIdx.x; i <= kDoneGroups; i += blockDim.x)
+            __hip_atomic_store(&done[i * kCounterPad], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Eq. (4) - Eq. (6): one scanline per wavefront
+// ---------------------------------------------------------------------------
+template <int K>
+__device__ __forceinline__ void cmp_swap_stage(uint64_t (&key)[K], int size, int stride, int lane) {
+    if (stride >= 64) {
+        const int ks = stride >> 6;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if ((k & ks) == 0) {
+                const int kp = k | ks;
+                const bool up = (((k * 64 + lane) & size) == 0);
+                const uint64_t a = key[k], b = key[kp];
+                const bool sw = up ? (a > b) : (a < b);
+                key[k] = sw ? b : a;
+                key[kp] = sw ? a : b;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint64_t o = xchg64(key[k], stride, lane);
+            const bool up = (((k * 64 + lane) & size) == 0);
+            const bool lower = ((lane & stride) == 0);
+            const bool lt = key[k] < o;
+            const uint64_t mn = lt ? key[k] : o;
+            const uint64_t mx = lt ? o : key[k];
+            key[k] = (lower == up) ? mn : mx;
+        }
+    }
+}
+
+template <int K>
+constexpr int log2_keys() { return K == 1 ? 6 : K == 2 ? 7 : K == 4 ? 8 : K == 8 ? 9 : 10; }
+
+// Ascending bitonic sort of 64*K keys; element e = k*64 + lane lives in key[k].
+template <int K>
+__device__ __forceinline__ void bitonic_sort(uint64_t (&key)[K], int lane) {
+    constexpr int LG = log2_keys<K>();
+#pragma unroll
+    for (int ls = 1; ls <= LG; ++ls) {
+#pragma unroll
+        for (int lt = ls - 1; lt >= 0; --lt) cmp_swap_stage<K>(key, 1 << ls, 1 << lt, lane);
+    }
+}
+
+struct WaveLds {
+    float* Vin;  // V by offset index e
+    float* Win;  // W by e (NaN where the sample is dropped)
+    uint32_t* Oin;  // f2ord(W) by e (the search keys of the co-rank merge)
+    float* Ws;   // W in sorted order (sort path)
+    float* Vs;   // V in sorted order (sort path)
+    int* rs;     // run starts (co-rank path), kMaxRunsCap + 1 entries
+};
+
+constexpr int kMaxRunsCap = 16;
+
+// Largest number of monotone runs for which the co-rank path is used
+// (above it the full sort is cheaper).
+template <int K>
+constexpr int max_runs() { return K == 1 ? 4 : K == 2 ? 5 : K == 4 ? 6 : K == 8 ? 8 : 12; }
+
+// (W, e) ordering of two samples: a before b
+__device__ __forceinline__ bool key_less(float wa, int ea, float wb, int eb) {
+    return wa < wb || (wa == wb && ea < eb);
+}
+
+template <int K>
+__device__ __forceinline__ void mark_hit(uint8_t* __restrict__ Mv, int W, int cx, int cy, float c,
+                                         float s, int g) {
+    const float gf = (float)g;
+    const int ix = (int)rintf(__fadd_rn((float)cx, __fmul_rn(c, gf)));
+    const int iy = (int)rintf(__fadd_rn((float)cy, __fmul_rn(s, gf)));
+    Mv[(size_t)iy * W + ix] = 1;
+}
+
+template <int K>
+__device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int W,
+                                         uint8_t* __restrict__ Mv, int cx, int cy, float c,
+                                         float s, float r, int h, const Thresholds& th,
+                                         const WaveLds& L, int lane) {
+    constexpr int N = 64 * K;
+    const int n = 2 * h + 1;
+    float wk[K];
+    uint64_t vmask[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        // branch-free: the gather address is clamped into the frame and the
+        // value of a dropped sample is discarded
+        const int e = k * 64 + lane;
+        const float gf = (float)(e - h);
+        const float px = __fadd_rn((float)cx, __fmul_rn(c, gf));
+        const float py = __fadd_rn((float)cy, __fmul_rn(s, gf));
+        const int ix = (int)rintf(px);
+        const int iy = (int)rintf(py);
+        const bool valid = (e < n) & (ix >= 0) & (ix < W) & (iy >= 0) & (iy < H);
+        const int cxi = min(max(ix, 0), W - 1), cyi = min(max(iy, 0), H - 1);
+        const float Vr = D[(size_t)cyi * W + cxi];
+        const float V = valid ? Vr : 0.0f;
+        const float w = valid ? __fsub_rn(gf, __fmul_rn(r, Vr)) : __int_as_float(0x7fc00000);
+        L.Vin[e] = V;
+        L.Win[e] = w;  // NaN: dropped
+        L.Oin[e] = f2ord(w);
+        wk[k] = w;
+        vmask[k] = __ballot(valid);
+    }
+    wave_lds_sync();
+    // descents W_e < W_{e-1} (both kept; NaN compares false): they split the
+    // kept samples into maximal runs of non-decreasing W
+    uint64_t dm[K];
+    int nvalid = 0, e_lo = -1, ndesc = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int e = k * 64 + lane;
+        const float wp = (e > 0) ? L.Win[e - 1] : __int_as_float(0x7fc00000);
+        dm[k] = __ballot(wk[k] < wp);
+        ndesc += __popcll(dm[k]);
+        nvalid += __popcll(vmask[k]);
+        if (vmask[k] && e_lo < 0) e_lo = k * 64 + __ffsll((unsigned long long)vmask[k]) - 1;
+    }
+    if (nvalid == 0) return;
+    const int e_hi = e_lo + nvalid - 1;  // the kept offsets are one contiguous run
+    const int R = ndesc + 1;
+
+    // sorted position of every kept sample (pk) and the sorted arrays Ws, Vs
+    int pk[K];
+    const float* Ws;
+    const float* Vs;
+    if (R == 1) {
+        // already in (W, g) order: sorted position p is offset e_lo + p
+#pragma unroll
+        for (int k = 0; k < K; ++k) pk[k] = k * 64 + lane - e_lo;
+        Ws = L.Win + e_lo;
+        Vs = L.Vin + e_lo;
+    } else if (R <= max_runs<K>()) {
+        // ---- co-rank merge: every run is sorted by (W, e); the sorted position
+        // of sample e is its index in its own run plus, for every other run,
+        // the number of that run's keys below (W_e, e) (binary search) ----
+        int before = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if ((dm[k] >> lane) & 1ull) L.rs[1 + before + (int)lanes_below(dm[k])] = k * 64 + lane;
+            before += __popcll(dm[k]);
+        }
+        if (lane == 0) {
+            L.rs[0] = e_lo;
+            L.rs[R] = e_hi + 1;
+        }
+        wave_lds_sync();
+        // longest run of the scanline bounds the search
+        int mmax = 1;
+        for (int rr = 0; rr < R; ++rr) mmax = max(mmax, L.rs[rr + 1] - L.rs[rr]);
+        const int top = 31 - __clz(mmax);
+        before = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int e0 = k * 64 + lane;
+            const bool valid = (vmask[k] >> lane) & 1ull;
+            const int e = valid ? e0 : e_lo;  // dropped lanes ride on a kept sample
+            const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+            const int own = valid ? before + __popcll(dm[k] & le) : 0;
+            before += __popcll(dm[k]);
+            const float We = wk[k];
+            const uint32_t oe = f2ord(We);
+            int pos = e - L.rs[own];
+            for (int i = 0; i + 1 < R; ++i) {
+                const int rr = i < own ? i : i + 1;
+                // keys of run rr below (W_e, e): O_j < ord(W_e), or <= for a run
+                // before e (equal W precede e); branch-free lower bound
+                const uint32_t T = oe + (rr < own ? 1u : 0u);
+                const int s0 = L.rs[rr];
+                int base = s0, len = L.rs[rr + 1] - s0;
+                for (int st = top; st >= 0; --st) {
+                    const int half = len >> 1;
+                    base = (L.Oin[base + half] < T) ? base + half : base;
+                    len -= half;
+                }
+                pos += base - s0 + ((L.Oin[base] < T) ? 1 : 0);
+            }
+            pk[k] = pos;
+            if (valid) {
+                L.Ws[pos] = We;
+                L.Vs[pos] = L.Vin[e];
+            }
+        }
+        Ws = L.Ws;
+        Vs = L.Vs;
+        wave_lds_sync();
+    } else {
+        // ---- many runs: bitonic sort of (W, e) keys ----
+        uint64_t key[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t e = (uint32_t)(k * 64 + lane);
+            key[k] = ((vmask[k] >> lane) & 1ull) ? (((uint64_t)f2ord(wk[k]) << 32) | e) : ~0ull;
+        }
+        bitonic_sort<K>(key, lane);
+        // the sorted array holds the origin of position p in key[k]; scatter the
+        // inverse (origin -> position) so the test below runs per kept sample
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int p = k * 64 + lane;
+            if (p < nvalid) {
+                const uint32_t o = (uint32_t)key[k];
+                L.Ws[p] = ord2f((uint32_t)(key[k] >> 32));
+                L.Vs[p] = L.Vin[o];
+                reinterpret_cast<int*>(L.Win)[o] = p;  // Win is free again: origin -> position
+            }
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int k = 0; k < K; ++k) pk[k] = reinterpret_cast<const int*>(L.Win)[min(k * 64 + lane, N - 1)];
+        Ws = L.Ws;
+        Vs = L.Vs;
+        wave_lds_sync();
+    }
+    // Eq. (5) at every kept sample's sorted position, Eq. (6) at its pixel
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int e = k * 64 + lane;
+        const bool valid = (vmask[k] >> lane) & 1ull;
+        const int p = valid ? pk[k] : 0;
+        const float Wp = Ws[p];
+        const float Vp = Vs[p];
+        bool hit = false;
+        for (int d = 1; d <= th.ns; ++d) {
+            const int jl = max(p - d, 0), jr = min(p + d, nvalid - 1);
+            const float wl = Ws[jl], vl = Vs[jl], wr = Ws[jr], vr = Vs[jr];
+            hit |= (p - d >= 0) & (fabsf(__fsub_rn(Wp, wl)) < th.zeta) & (__fsub_rn(vl, Vp) > th.beta);
+            hit |= (p + d < nvalid) & (fabsf(__fsub_rn(Wp, wr)) < th.zeta) &
+                   (__fsub_rn(vr, Vp) > th.beta);
+        }
+        if (valid & hit) mark_hit<K>(Mv, W, cx, cy, c, s, e - h);
+    }
+    wave_lds_sync();
+}
+
+struct ViewList {
+    int v[OCCL_MAX_VIEWS];
+};
+
+// Flat round-robin over every (view, candidate) pair of the listed views.
+// KMAX = 2 serves the views of register classes K = 1 and 2; larger classes
+// are launched one per class.
+template <int KMAX>
+constexpr int waves_per_block() { return KMAX >= 16 ? 2 : 4; }
+
+template <int KMAX>
+__global__ __launch_bounds__(64 * waves_per_block<KMAX>()) void k_scanlines(
+    const float* __restrict__ D, int H, int W, uint8_t* __restrict__ M, ViewTable vt,
+    Thresholds th, ViewList vl, int n_list, ListLayout ll, const uint32_t* __restrict__ lists,
+    const int32_t* __restrict__ gpre) {
+    constexpr int WPB = waves_per_block<KMAX>();
+    constexpr int NT = 64 * WPB;
+    __shared__ float lds[WPB][4][64 * KMAX];
+    __shared__ uint32_t okeys[WPB][64 * KMAX];
+    __shared__ int runs[WPB][kMaxRunsCap + 1];
+    __shared__ int pre[kMaxSegments + 1];  // exclusive prefix over (listed view, copy)
+    __shared__ int vbase[OCCL_MAX_VIEWS + 1];
+    const int C = ll.copies;
+    const int nseg = n_list * C;
+    if (threadIdx.x < 64) {  // per listed view: its candidates and their running sum
+        const int ln = threadIdx.x;
+        int tot = 0;
+        if (ln < n_list) {
+            const int v = vl.v[ln];
+            tot = gpre[(v + 1) * C] - gpre[v * C];
+        }
+        int x = tot;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(x, d, 64);
+            if (ln >= d) x += y;
+        }
+        vbase[ln] = x - tot;
+        if (ln == 63) vbase[64] = x;
+    }
+    __syncthreads();
+    for (int sg = threadIdx.x; sg < nseg; sg += NT) {
+        const int i = sg / C, v = vl.v[i];
+        pre[sg] = vbase[i] + gpre[v * C + sg % C] - gpre[v * C];
+    }
+    if (threadIdx.x == 0) pre[nseg] = vbase[64];
+    __syncthreads();
+    const int total = pre[nseg];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const WaveLds L{lds[wave][0], lds[wave][1], okeys[wave], lds[wave][2], lds[wave][3], runs[wave]};
+    // each wavefront takes one contiguous chunk of the flat work list, so the
+    // segment of consecutive items is found by stepping forward
+    const int nw = gridDim.x * WPB;
+    const int gw = blockIdx.x * WPB + wave;
+    const int chunk = (total + nw - 1) / nw;
+    const int t_end = min(total, (gw + 1) * chunk);
+    int lo = 0;
+    if (gw * chunk < t_end) {  // segment of the first item: last with pre <= t
+        int hi = nseg - 1;
+        const int t0 = gw * chunk;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (pre[mid] <= t0) lo = mid; else hi = mid - 1;
+        }
+    }
+    for (int t = gw * chunk; t < t_end; ++t) {
+        while (lo + 1 < nseg && pre[lo + 1] <= t) ++lo;
+        const int i = lo / ll.copies;
+        const int v = vl.v[i];
+        const int seg = v * ll.copies + lo % ll.copies;
+        const uint32_t pix = lists[(size_t)seg * ll.cap + (size_t)(t - pre[lo])];
+        const int cy = (int)(pix / (uint32_t)W);
+        const int cx = (int)(pix - (uint32_t)cy * (uint32_t)W);
+        const int h = vt.h[v];
+        uint8_t* Mv = M + (size_t)v * H * W;
+        const int K = lanes_per_scanline_k(2 * h + 1);
+        if constexpr (KMAX == 2) {
+            if (K == 1)
+                scanline<1>(D, H, W, Mv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, th, L, lane);
+            else
+                scanline<2>(D, H, W, Mv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, th, L, lane);
+        } else {
+            scanline<KMAX>(D, H, W, Mv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, th, L, lane);
+        }
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+ListLayout make_list_layout(int H, int W, int n_views) {
+    ListLayout ll;
+    const int block_rows = (H + kEdgeRows - 1) / kEdgeRows;
+    int copies = kMaxSegments / (n_views > 0 ? n_views : 1);
+    if (copies > kMaxCopies) copies = kMaxCopies;
+    if (copies > block_rows) copies = block_rows;
+    if (copies < 1) copies = 1;
+    ll.block_rows_per_copy = (block_rows + copies - 1) / copies;
+    ll.copies = (block_rows + ll.block_rows_per_copy - 1) / ll.block_rows_per_copy;
+    ll.cap = (size_t)ll.block_rows_per_copy * kEdgeRows * (size_t)W;
+    return ll;
+}
+
+hipError_t launch_edges_candidates(hipStream_t st, const float* D, int H, int W, uint8_t* M,
+                                   int n_views, const ViewTable& vt, float q_min,
+                                   const ListLayout& ll, uint32_t* lists, int32_t* counts,
+                                   int32_t* prefix) {
+    const int vec = ((W % 4) == 0 && (reinterpret_cast<uintptr_t>(D) % 16) == 0 &&
+                     (reinterpret_cast<uintptr_t>(M) % 4) == 0)
+                        ? 1
+                        : 0;
+    dim3 grid((W + kEdgeCols - 1) / kEdgeCols, (H + kEdgeRows - 1) / kEdgeRows);
+    hipLaunchKernelGGL(k_edges_candidates, grid, dim3(kEdgeThreads), 0, st, D, H, W, M, n_views,
+                       vt, q_min, ll, lists, counts, prefix, vec);
+    return hipGetLastError();
+}
+
+hipError_t launch_scanlines(hipStream_t st, const float* D, int H, int W, uint8_t* M,
+                            const ViewTable& vt, const Thresholds& th, const int* views, int n_list,
+                            int kclass, const ListLayout& ll, const uint32_t* lists,
+                            const int32_t* prefix, int n_blocks) {
+    if (n_list <= 0) return hipSuccess;
+    ViewList vl{};
+    for (int i = 0; i < n_list; ++i) vl.v[i] = views[i];
+    const dim3 grid(n_blocks);
+    switch (kclass) {
+        case 2:
+            hipLaunchKernelGGL(k_scanlines<2>, grid, dim3(64 * waves_per_block<2>()), 0, st, D, H, W,
+                               M, vt, th, vl, n_list, ll, lists, prefix);
+            break;
+        case 4:
+            hipLaunchKernelGGL(k_scanlines<4>, grid, dim3(64 * waves_per_block<4>()), 0, st, D, H, W,
+                               M, vt, th, vl, n_list, ll, lists, prefix);
+            break;
+        case 8:
+            hipLaunchKernelGGL(k_scanlines<8>, grid, dim3(64 * waves_per_block<8>()), 0, st, D, H, W,
+                               M, vt, th, vl, n_list, ll, lists, prefix);
+            break;
+        case 16:
+            hipLaunchKernelGGL(k_scanlines<16>, grid, dim3(64 * waves_per_block<16>()), 0, st, D, H,
+                               W, M, vt, th, vl, n_list, ll, lists, prefix);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace occl

@@ -1,0 +1,140 @@
+// k_util.hip -- small helper kernels: statistics of D (automatic scan length,
+// input validation), the edge magnitude / angle maps of Eq. (1) as outputs,
+// and the confusion counts behind Eq. (7).
+#include "occl_internal.h"
+
+namespace occl {
+namespace {
+
+__device__ __forceinline__ uint32_t ford(float w) {
+    const uint32_t u = __float_as_uint(w);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__global__ void k_stats_init(uint32_t* dev) {
+    if (threadIdx.x == 0) {
+        dev[0] = 0xffffffffu;  // running min (orderable)
+        dev[1] = 0u;           // running max (orderable)
+        dev[2] = 0u;           // non-finite count
+    }
+}
+
+__global__ __launch_bounds__(256) void k_stats(const float* __restrict__ D, size_t n,
+                                               uint32_t* __restrict__ dev) {
+    uint32_t mn = 0xffffffffu, mx = 0u, bad = 0u;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const float d = D[i];
+        if (!isfinite(d)) {
+            ++bad;
+            continue;
+        }
+        const uint32_t o = ford(d);
+        mn = o < mn ? o : mn;
+        mx = o > mx ? o : mx;
+    }
+    for (int m = 32; m > 0; m >>= 1) {
+        const uint32_t a = (uint32_t)__shfl_xor((int)mn, m, 64);
+        const uint32_t b = (uint32_t)__shfl_xor((int)mx, m, 64);
+        const uint32_t c = (uint32_t)__shfl_xor((int)bad, m, 64);
+        mn = a < mn ? a : mn;
+        mx = b > mx ? b : mx;
+        bad += c;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(&dev[0], mn);
+        atomicMax(&dev[1], mx);
+        if (bad) atomicAdd(&dev[2], bad);
+    }
+}
+
+// Correctly rounded fp32 square root: the hardware estimate is within one
+// ulp; the neighbour whose rounding interval holds sqrt(q) is selected with
+// exact double arithmetic (a midpoint has 25 significant bits, its square 50).
+__device__ __forceinline__ float sqrt_cr(float q) {
+    if (!(q > 0.0f) || isinf(q)) return __builtin_sqrtf(q);
+    const float s = __builtin_sqrtf(q);
+    const float lo = nextafterf(s, 0.0f);
+    const float hi = nextafterf(s, INFINITY);
+    const double qd = (double)q;
+    const double mh = 0.5 * ((double)s + (double)hi);
+    const double ml = 0.5 * ((double)lo + (double)s);
+    if (mh * mh <= qd) return hi;
+    if (ml * ml >= qd) return lo;
+    return s;
+}
+
+__global__ __launch_bounds__(256) void k_edges_out(const float* __restrict__ D, int H, int W,
+                                                   float* __restrict__ E, float* __restrict__ A) {
+    const size_t n = (size_t)H * W;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int y = (int)(i / W), x = (int)(i % W);
+        const float d = D[i];
+        const float ex = (x + 1 < W) ? __fsub_rn(D[i + 1], d) : 0.0f;
+        const float ey = (y + 1 < H) ? __fsub_rn(D[i + W], d) : 0.0f;
+        if (E) E[i] = sqrt_cr(__fadd_rn(__fmul_rn(ex, ex), __fmul_rn(ey, ey)));
+        if (A) A[i] = atan2f(ey, ex);
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
+
+__global__ __launch_bounds__(256) void k_confusion(const uint8_t* __restrict__ pred,
+                                                   const uint8_t* __restrict__ ref, size_t n,
+                                                   unsigned long long* __restrict__ out) {
+    unsigned long long tp = 0, fp = 0, fn = 0, tn = 0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const bool p = pred[i] != 0, t = ref[i] != 0;
+        tp += (p && t);
+        fp += (p && !t);
+        fn += (!p && t);
+        tn += (!p && !t);
+    }
+    for (int m = 32; m > 0; m >>= 1) {
+        tp += __shfl_xor(tp, m, 64);
+        fp += __shfl_xor(fp, m, 64);
+        fn += __shfl_xor(fn, m, 64);
+        tn += __shfl_xor(tn, m, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&out[0], tp);
+        atomicAdd(&out[1], fp);
+        atomicAdd(&out[2], fn);
+        atomicAdd(&out[3], tn);
+    }
+}
+
+inline int grid_for(size_t n, int per_block, int cap) {
+    size_t g = (n + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > (size_t)cap) g = cap;
+    return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_scan_stats(hipStream_t st, const float* D, size_t n, uint32_t* dev) {
+    hipLaunchKernelGGL(k_stats_init, dim3(1), dim3(64), 0, st, dev);
+    hipLaunchKernelGGL(k_stats, dim3(grid_for(n, 256 * 8, 2048)), dim3(256), 0, st, D, n, dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_edges_out(hipStream_t st, const float* D, int H, int W, float* E, float* A) {
+    const size_t n = (size_t)H * W;
+    hipLaunchKernelGGL(k_edges_out, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, D, H, W, E, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_confusion(hipStream_t st, const uint8_t* pred, const uint8_t* ref, size_t n,
+                            unsigned long long* dev4) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, dev4, 4);
+    hipLaunchKernelGGL(k_confusion, dim3(grid_for(n, 256 * 16, 4096)), dim3(256), 0, st, pred, ref,
+                       n, dev4);
+    return hipGetLastError();
+}
+
+}  // namespace occl

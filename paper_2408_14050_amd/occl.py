@@ -1,0 +1,261 @@
+"""Thin ctypes binding of libocclusion.so (include/occl.h).
+
+Argument marshalling only: every step of the detector runs in the HIP
+kernels of the library.  Tensors are torch tensors on a ROCm device; torch
+provides the device memory and the stream, nothing else.  There is no CPU
+fallback: if the library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libocclusion.so")
+
+OCCL_OK = 0
+STATUS = {0: "OK", -1: "INVALID_ARG", -2: "OUT_OF_MEMORY", -3: "HIP", -4: "UNSUPPORTED",
+          -5: "NO_MODEL", -6: "STATE"}
+OCCL_MAX_VIEWS = 64
+OCCL_MAX_SCAN_LEN = 1023
+FLAG_SYNC = 1
+FLAG_VALIDATE_INPUT = 2
+FLAG_USE_CNN = 4
+
+
+class OcclError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class occl_params(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32),
+        ("edge_thr", C.c_float),
+        ("disp_thr", C.c_float),
+        ("dist_thr", C.c_float),
+        ("neighbours", C.c_int32),
+        ("scan_len", C.c_int32),
+        ("scan_len_per_view", C.POINTER(C.c_int32)),
+        ("flags", C.c_uint32),
+        ("cnn_lo", C.c_float),
+        ("cnn_hi", C.c_float),
+    ]
+
+
+class occl_frame(C.Structure):
+    _fields_ = [
+        ("D", C.c_void_p),
+        ("H", C.c_int32),
+        ("W", C.c_int32),
+        ("M", C.c_void_p),
+        ("scan_len_per_view", C.POINTER(C.c_int32)),
+    ]
+
+
+_lib = None
+
+# name -> (restype, argtypes); the same names as the C ABI
+_SIGS = {
+    "occl_params_default": (None, [C.POINTER(occl_params)]),
+    "occl_init": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_void_p, C.c_size_t, C.c_int32]),
+    "occl_detect": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                              C.POINTER(C.c_double), C.POINTER(C.c_float), C.POINTER(occl_params),
+                              C.c_void_p]),
+    "occl_detect_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(occl_frame), C.c_int32,
+                                      C.POINTER(C.c_double), C.POINTER(C.c_float),
+                                      C.POINTER(occl_params)]),
+    "occl_last_candidate_counts": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_int32]),
+    "occl_edges": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
+    "occl_confusion": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                 C.POINTER(C.c_uint64)]),
+    "occl_sync": (C.c_int, [C.c_void_p]),
+    "occl_release": (C.c_int, [C.c_void_p]),
+    "occl_status_string": (C.c_char_p, [C.c_int]),
+    "occl_last_error": (C.c_char_p, [C.c_void_p]),
+    "occl_direction": (C.c_int, [C.c_double, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
+    "occl_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
+    "occl_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+}
+STAGES = ("edges", "scanlines", "cnn", "fallback")
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def lib():
+    """Loads libocclusion.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise OcclError(-3, f"{LIB_PATH} is missing: run __graft_entry__.build() "
+                                "(python -m paper_2408_14050_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def params(edge_thr=1.0, disp_thr=0.5, dist_thr=1.0, neighbours=1, scan_len=0,
+           scan_len_per_view=None, flags=0, cnn_lo=0.05, cnn_hi=0.95):
+    p = occl_params()
+    lib().occl_params_default(C.byref(p))
+    p.edge_thr, p.disp_thr, p.dist_thr = float(edge_thr), float(disp_thr), float(dist_thr)
+    p.neighbours, p.scan_len, p.flags = int(neighbours), int(scan_len), int(flags)
+    p.cnn_lo, p.cnn_hi = float(cnn_lo), float(cnn_hi)
+    keep = None
+    if scan_len_per_view is not None:
+        keep = np.ascontiguousarray(np.atleast_1d(scan_len_per_view), dtype=np.int32)
+        p.scan_len_per_view = keep.ctypes.data_as(C.POINTER(C.c_int32))
+    p._keep = keep  # keep the host array alive as long as the struct
+    return p
+
+
+def direction(angle_deg: float):
+    c, s = C.c_float(), C.c_float()
+    st = lib().occl_direction(float(angle_deg), C.byref(c), C.byref(s))
+    if st != OCCL_OK:
+        raise OcclError(st, "occl_direction")
+    return np.float32(c.value), np.float32(s.value)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Context:
+    """An occl_ctx bound to one ROCm device and one HIP stream."""
+
+    def __init__(self, device: int = 0, stream=None, max_pixels_hint: int = 0,
+                 max_views_hint: int = 0):
+        import torch
+        self._torch = torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = C.c_void_p()
+        st = lib().occl_init(C.byref(h), int(device), C.c_void_p(stream.cuda_stream),
+                             int(max_pixels_hint), int(max_views_hint))
+        if st != OCCL_OK:
+            raise OcclError(st, "occl_init")
+        self.h = h
+        self.device = device
+
+    # -- helpers -----------------------------------------------------------
+    def _check(self, st, what):
+        if st != OCCL_OK:
+            msg = lib().occl_last_error(self.h)
+            raise OcclError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    @staticmethod
+    def _views(angles, ratios):
+        a = np.ascontiguousarray(np.atleast_1d(angles), dtype=np.float64)
+        r = np.ascontiguousarray(np.atleast_1d(ratios), dtype=np.float32)
+        if a.shape != r.shape:
+            raise ValueError("angles and ratios differ in length")
+        return a, r
+
+    # -- API ---------------------------------------------------------------
+    def occl_detect(self, D, angles, ratios, prm: occl_params, M=None):
+        """D: float32 [H, W] device tensor; returns M uint8 [V, H, W]."""
+        torch = self._torch
+        a, r = self._views(angles, ratios)
+        H, W = (int(D.shape[0]), int(D.shape[1])) if D.dim() == 2 else (0, 0)
+        if M is None:
+            M = torch.empty((a.shape[0], H, W), dtype=torch.uint8, device=D.device)
+        st = lib().occl_detect(self.h, _ptr(D), H, W, int(a.shape[0]),
+                               a.ctypes.data_as(C.POINTER(C.c_double)),
+                               r.ctypes.data_as(C.POINTER(C.c_float)), C.byref(prm), _ptr(M))
+        self._check(st, "occl_detect")
+        return M
+
+    def occl_detect_batched(self, frames, angles, ratios, prm: occl_params):
+        """frames: list of (D, M, scan_len_per_view or None)."""
+        a, r = self._views(angles, ratios)
+        arr = (occl_frame * max(1, len(frames)))()
+        keep = []
+        for i, (D, M, Ls) in enumerate(frames):
+            arr[i].D = D.data_ptr()
+            arr[i].H, arr[i].W = int(D.shape[0]), int(D.shape[1])
+            arr[i].M = M.data_ptr()
+            if Ls is not None:
+                l = np.ascontiguousarray(Ls, dtype=np.int32)
+                keep.append(l)
+                arr[i].scan_len_per_view = l.ctypes.data_as(C.POINTER(C.c_int32))
+        st = lib().occl_detect_batched(self.h, len(frames), arr, int(a.shape[0]),
+                                       a.ctypes.data_as(C.POINTER(C.c_double)),
+                                       r.ctypes.data_as(C.POINTER(C.c_float)), C.byref(prm))
+        self._check(st, "occl_detect_batched")
+
+    def occl_last_candidate_counts(self, n_views: int):
+        out = np.zeros(n_views, np.int64)
+        st = lib().occl_last_candidate_counts(self.h, out.ctypes.data_as(C.POINTER(C.c_int64)),
+                                              int(n_views))
+        self._check(st, "occl_last_candidate_counts")
+        return out
+
+    def occl_edges(self, D, E=None, A=None):
+        st = lib().occl_edges(self.h, _ptr(D), int(D.shape[0]), int(D.shape[1]), _ptr(E), _ptr(A))
+        self._check(st, "occl_edges")
+        return E, A
+
+    def occl_confusion(self, pred, ref):
+        out = np.zeros(4, np.uint64)
+        st = lib().occl_confusion(self.h, _ptr(pred), _ptr(ref), int(pred.numel()),
+                                  out.ctypes.data_as(C.POINTER(C.c_uint64)))
+        self._check(st, "occl_confusion")
+        return {"tp": int(out[0]), "fp": int(out[1]), "fn": int(out[2]), "tn": int(out[3])}
+
+    def occl_profile_enable(self, enable: bool = True):
+        self._check(lib().occl_profile_enable(self.h, int(bool(enable))), "occl_profile_enable")
+
+    def occl_profile_read(self):
+        """{stage: (total_ms, launches)} since the last enable."""
+        ms = np.zeros(len(STAGES), np.float64)
+        n = np.zeros(len(STAGES), np.int64)
+        st = lib().occl_profile_read(self.h, ms.ctypes.data_as(C.POINTER(C.c_double)),
+                                     n.ctypes.data_as(C.POINTER(C.c_int64)))
+        self._check(st, "occl_profile_read")
+        return {s: (float(ms[i]), int(n[i])) for i, s in enumerate(STAGES)}
+
+    def occl_sync(self):
+        self._check(lib().occl_sync(self.h), "occl_sync")
+
+    def occl_release(self):
+        if self.h:
+            st = lib().occl_release(self.h)
+            self.h = None
+            if st != OCCL_OK:
+                raise OcclError(st, "occl_release")
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().occl_release(self.h)
+        except Exception:
+            pass
+
+
+@dataclass
+class SceneRun:
+    M: object
+    n_cand: np.ndarray
+
+
+def detect_scene(ctx: Context, sc, D=None, want_counts=False, flags=FLAG_SYNC):
+    """Runs one generated scene (paper_2408_14050_amd.scenes.Scene) on the GPU."""
+    import torch
+    if D is None:
+        D = torch.from_numpy(sc.D).to(f"cuda:{ctx.device}")
+    p = params(**sc.params, scan_len_per_view=sc.scan_len, flags=flags)
+    M = ctx.occl_detect(D, sc.angles, sc.ratios, p)
+    nc = ctx.occl_last_candidate_counts(sc.n_views) if want_counts else None
+    return SceneRun(M, nc)
