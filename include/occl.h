@@ -128,6 +128,36 @@ occl_status occl_detect_batched(occl_ctx* ctx, int32_t n_frames, const occl_fram
                                 int32_t n_views, const double* angles_deg, const float* ratios,
                                 const occl_params* params);
 
+/* Launch shape of the exact path: edge-pass rows (wavefronts) per block and
+ * persistent scanline blocks per compute unit. */
+typedef struct {
+    int32_t edge_rows;           /* 1, 2, 4, 8 or 16 */
+    int32_t scan_blocks_per_cu;  /* 1..64 */
+    float ms;                    /* measured time per call of the chosen shape (autotune output) */
+} occl_tune;
+
+/* Autotuner: times the candidate launch shapes on this frame (each trial
+ * computes the full masks into M, so M ends with the correct result) and
+ * records the fastest for frames of the same size class (log2 of H*W), view
+ * count and scan class; later calls in that bucket use it.  `reps` timed
+ * calls per shape (<= 0: 10).  `out` (optional) receives the choice.
+ * Synchronises the stream. */
+occl_status occl_autotune(occl_ctx* ctx, const float* D, int32_t H, int32_t W, int32_t n_views,
+                          const double* angles_deg, const float* ratios, const occl_params* params,
+                          uint8_t* M, int32_t reps, occl_tune* out);
+
+/* The same for a batch (1..1024 non-empty frames); the bucket is the batch's
+ * total pixel count, view count and scan class. */
+occl_status occl_autotune_batched(occl_ctx* ctx, int32_t n_frames, const occl_frame* frames,
+                                  int32_t n_views, const double* angles_deg, const float* ratios,
+                                  const occl_params* params, int32_t reps, occl_tune* out);
+
+/* Writes / reads the tuned launch shapes as text ("bucket edge_rows
+ * scan_blocks_per_cu" per line).  Loading validates every line and merges
+ * the entries into the context; a malformed file changes nothing. */
+occl_status occl_tune_save(const occl_ctx* ctx, const char* path);
+occl_status occl_tune_load(occl_ctx* ctx, const char* path);
+
 /* Candidates per view of the most recent occl_detect (host int64 [n_views]);
  * synchronises the stream. */
 occl_status occl_last_candidate_counts(occl_ctx* ctx, int64_t* out, int32_t n_views);
@@ -156,7 +186,8 @@ occl_status occl_release(occl_ctx* ctx);
 #define OCCL_STAGE_SCANLINES 1  /* k_scanlines: Eqs. (4)-(6) */
 #define OCCL_STAGE_CNN 2        /* learned tile proposal (pack, convolutions, routing) */
 #define OCCL_STAGE_FALLBACK 3   /* exact fallback on uncertain tiles */
-#define OCCL_N_STAGES 4
+#define OCCL_STAGE_BATCHED 4    /* one graph launch of occl_detect_batched */
+#define OCCL_N_STAGES 5
 occl_status occl_profile_enable(occl_ctx* ctx, int32_t enable);
 occl_status occl_profile_read(occl_ctx* ctx, double* ms /* [OCCL_N_STAGES] */,
                               int64_t* launches /* [OCCL_N_STAGES] */);

@@ -1,30 +1,31 @@
 // k_exact.hip -- gfx950 kernels of the exact detector (Sec. 3, Eqs. 1-6).
 //
-// Two launches per frame (plus one per extra register class of long scans):
-//   k_edges_candidates  dense, HBM-bound pass over D (Eqs. 1-2).  One wavefront
-//                       per 256-pixel row segment, 4 consecutive pixels per
-//                       lane (one float4 of row y and one of row y+1).  The
-//                       candidates of every view are compacted with ballots
-//                       and appended to that view's global list with a single
-//                       atomic per wavefront.  The same pass writes the zero
-//                       background of every mask, so each mask byte costs
-//                       one streaming write.  Its last block turns the
-//                       segment counters into a prefix for the next launch
-//                       and clears them for the next frame.
-//   k_scanlines<KMAX>   one wavefront per candidate scanline (Eqs. 4-6), the
-//                       (view, candidate) pairs handed out flat and
-//                       round-robin, so long and short lists balance.  A
-//                       scanline of n <= 64*K samples holds K samples per lane.
-//                       Sorting by (W, g): if W never descends along g the
-//                       samples are already in sorted order; with exactly one
-//                       descent the two ascending runs are merged by one
-//                       bitonic merge (the second run reversed); otherwise a
-//                       full bitonic sort.  Compare-exchange partners are
-//                       reached with DPP and permlane swaps (no LDS round
-//                       trip).  The sorted W and V go through LDS for the
-//                       neighbour test of Eq. (5); hits are byte stores of 1
-//                       into the cleared mask, so concurrent scanlines need
-//                       no atomics and the result does not depend on order.
+// Two launches per frame (plus one per extra register class of long scans);
+// the batched forms run every frame of a batch in one launch each and are
+// captured together in one graph.
+//   edge pass        dense, HBM-bound pass over D (Eqs. 1-2).  One wavefront
+//                    per 256-pixel row segment, 4 consecutive pixels per lane
+//                    (one float4 of row y and one of row y+1).  The
+//                    candidates of every view are compacted with ballots and
+//                    appended to the list of their row band with a single
+//                    atomic per wavefront.  The same pass writes the zero
+//                    background of every mask, so each mask byte costs one
+//                    streaming write.  The last block of a frame turns the
+//                    segment counters into a class-major prefix for the
+//                    scanline pass and clears them for the next frame.
+//   scanline pass    one wavefront per candidate scanline (Eqs. 4-6), the
+//                    (view, candidate) pairs handed out flat, one contiguous
+//                    chunk per wavefront, so long and short lists balance.
+//                    A scanline of n <= 64*K samples holds K samples per lane.
+//                    Ordering by (W, g): W split into maximal non-decreasing
+//                    runs; one run is already sorted; up to a few runs are
+//                    merged by co-ranks (binary search of every sample in the
+//                    other runs); otherwise a bitonic sort whose partners are
+//                    reached with DPP and permlane swaps.  The sorted W and V
+//                    go through LDS for the neighbour test of Eq. (5); hits
+//                    are byte stores of 1 into the cleared mask, so
+//                    concurrent scanlines need no atomics and the result
+//                    does not depend on order.
 //
 // Every fp32 operation that feeds a decision is an explicitly rounded
 // intrinsic (__fmul_rn, __fadd_rn, __fsub_rn) and the library is built with
@@ -96,27 +97,31 @@ __device__ __forceinline__ float ord2f(uint32_t o) {
 // ---------------------------------------------------------------------------
 // Eq. (1) + Eq. (2): edges, candidates, mask clear
 // ---------------------------------------------------------------------------
-// Exclusive prefix of the segment counters, computed once per frame by the
-// last block of the edge pass, which also clears the counters and the block
-// counter for the next frame (so no separate clearing launch is needed and
-// the sequence can be replayed from a captured graph).  `prefix` gets
-// nseg + 1 entries.
-__device__ void finish_segments(int32_t* __restrict__ counts, int32_t* __restrict__ prefix,
-                                int nseg) {
-    __shared__ int wsum[kEdgeThreads / 64];
+// Exclusive prefix (class-major order) of the frame's segment counters,
+// computed once per frame by the last block of the edge pass, which also
+// clears the counters for the next frame (so no separate clearing launch is
+// needed and the sequence can be replayed from a captured graph).
+__device__ void finish_frame(const FrameDesc& f, int n_views) {
+    __shared__ int wsum[kMaxEdgeRows];
+    const int NT = blockDim.x;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    constexpr int PER = (kMaxSegments + kEdgeThreads - 1) / kEdgeThreads;
-    int c[PER];
+    const int C = f.ll.copies;
+    const int nseg = n_views * C;
+    const int per = (nseg + NT - 1) / NT;
+    constexpr int PERMAX = kMaxSegments / 64;
+    int c[PERMAX];
     int sum = 0;
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        const int sg = t * PER + j;
-        c[j] = (sg < nseg) ? __hip_atomic_load(&counts[sg * kCounterPad], __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT)
-                           : 0;
+    for (int j = 0; j < PERMAX; ++j) {
+        const int sg = t * per + j;
+        c[j] = 0;
+        if (j < per && sg < nseg) {
+            const int g = f.vord[sg / C] * C + sg % C;
+            c[j] = __hip_atomic_load(&f.counts[g * kCounterPad], __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+        }
         sum += c[j];
     }
-    // inclusive scan of the per-thread sums: within the wavefront, then across
     int x = sum;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
@@ -125,33 +130,37 @@ __device__ void finish_segments(int32_t* __restrict__ counts, int32_t* __restric
     }
     if (lane == 63) wsum[wave] = x;
     __syncthreads();
-    int wbase = 0;
-    for (int w = 0; w < wave; ++w) wbase += wsum[w];
-    int run = wbase + x - sum;  // exclusive prefix of this thread's first segment
+    int run = x - sum;
+    for (int w = 0; w < wave; ++w) run += wsum[w];
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        const int sg = t * PER + j;
-        if (sg < nseg) {
-            prefix[sg] = run;
-            __hip_atomic_store(&counts[sg * kCounterPad], 0, __ATOMIC_RELAXED,
+    for (int j = 0; j < PERMAX; ++j) {
+        const int sg = t * per + j;
+        if (j < per && sg < nseg) {
+            f.prefix[sg] = run;
+            const int g = f.vord[sg / C] * C + sg % C;
+            __hip_atomic_store(&f.counts[g * kCounterPad], 0, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         }
         run += c[j];
     }
-    if (t == kEdgeThreads - 1) prefix[nseg] = run;
+    if (t == NT - 1) f.prefix[nseg] = run;
 }
 
-// E > gamma is decided without a square root: q = E_x^2 + E_y^2 (fp32, same
-// rounding as the definition) is compared with q_min, the smallest fp32 q
-// whose correctly rounded square root exceeds gamma (computed on the host).
-// This is exactly sqrt_rn(q) > gamma, since sqrt_rn is monotone.
-__global__ __launch_bounds__(kEdgeThreads) void k_edges_candidates(
-    const float* __restrict__ D, int H, int W, uint8_t* __restrict__ M, int n_views, ViewTable vt,
-    float q_min, ListLayout ll, uint32_t* __restrict__ lists, int32_t* __restrict__ counts,
-    int32_t* __restrict__ prefix, int vec) {
+// One edge-pass block (bx, by) of frame f: blockDim.x / 64 wavefronts on
+// consecutive rows.  E > gamma is decided without a square root:
+// q = E_x^2 + E_y^2 (fp32, same rounding as the definition) is compared with
+// q_min, the smallest fp32 q whose correctly rounded square root exceeds
+// gamma (computed on the host), which is exactly sqrt_rn(q) > gamma.
+__device__ void edge_block(const FrameDesc& f, int bx, int by, int n_views, const ViewTable& vt,
+                           float q_min) {
+    const float* __restrict__ D = f.D;
+    const int H = f.H, W = f.W;
     const int lane = threadIdx.x & 63;
-    const int y = blockIdx.y * kEdgeRows + (threadIdx.x >> 6);
-    const int x0 = blockIdx.x * kEdgeCols + lane * 4;
+    const int rows = blockDim.x >> 6;
+    const int y = by * rows + (threadIdx.x >> 6);
+    const int x0 = bx * kEdgeCols + lane * 4;
+    const bool vec = ((W & 3) == 0) && ((reinterpret_cast<uintptr_t>(D) & 15) == 0) &&
+                     ((reinterpret_cast<uintptr_t>(f.M) & 3) == 0);
     const bool row_ok = (y < H);
     const bool live = row_ok && x0 < W;
     if (row_ok) {
@@ -191,7 +200,7 @@ __global__ __launch_bounds__(kEdgeThreads) void k_edges_candidates(
             any |= strong[j];
         }
         if (__ballot(any)) {
-            const int seg0 = (int)blockIdx.y / ll.block_rows_per_copy;
+            const int band = by / f.ll.block_rows_per_copy;
             for (int v = 0; v < n_views; ++v) {
                 const float c = vt.c[v], s = vt.s[v];
                 uint64_t b[4];
@@ -205,13 +214,13 @@ __global__ __launch_bounds__(kEdgeThreads) void k_edges_candidates(
                 }
                 const int tot = __popcll(b[0]) + __popcll(b[1]) + __popcll(b[2]) + __popcll(b[3]);
                 if (tot == 0) continue;
-                int off = (int)(lanes_below(b[0]) + lanes_below(b[1]) + lanes_below(b[2]) +
-                                lanes_below(b[3]));
-                const int seg = v * ll.copies + seg0;
+                const int off = (int)(lanes_below(b[0]) + lanes_below(b[1]) + lanes_below(b[2]) +
+                                      lanes_below(b[3]));
+                const int seg = v * f.ll.copies + band;
                 int base = 0;
-                if (lane == 0) base = atomicAdd(&counts[seg * kCounterPad], tot);
+                if (lane == 0) base = atomicAdd(&f.counts[seg * kCounterPad], tot);
                 base = __builtin_amdgcn_readlane(base, 0);
-                uint32_t* dst = lists + (size_t)seg * ll.cap + base + off;
+                uint32_t* dst = f.lists + (size_t)seg * f.ll.cap + base + off;
                 const uint32_t pix = (uint32_t)y * (uint32_t)W + (uint32_t)x0;
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
@@ -221,7 +230,7 @@ __global__ __launch_bounds__(kEdgeThreads) void k_edges_candidates(
         if (live) {
             const size_t HW = (size_t)H * W;
             for (int v = 0; v < n_views; ++v) {
-                uint8_t* mrow = M + v * HW + (size_t)y * W;
+                uint8_t* mrow = f.M + v * HW + (size_t)y * W;
                 if (vec) {
                     *reinterpret_cast<uint32_t*>(mrow + x0) = 0u;
                 } else {
@@ -232,22 +241,22 @@ __global__ __launch_bounds__(kEdgeThreads) void k_edges_candidates(
             }
         }
     }
-    // The last block to finish turns the counters into the frame's prefix.
-    // No fence is needed: every segment atomic of this block has returned
-    // (its result addressed the list stores) before the completion atomic,
+    // The last block of the frame turns the counters into the frame's prefix.
+    // Completion is counted in two levels (kDoneGroups group counters, then
+    // one top counter) so no single address takes one atomic per block.  No
+    // fence is needed: every segment atomic of this block has returned (its
+    // result addressed the list stores) before the completion atomic,
     // device-scope atomics are performed at the coherence point, the last
     // block reads the counters with atomic loads, and the list entries are
     // only read by the next launch.
-    // Completion is counted in two levels (kDoneGroups group counters, then
-    // one top counter) so no single address takes one atomic per block.
     __shared__ int s_last;
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned* done = reinterpret_cast<unsigned*>(counts + kMaxSegments * kCounterPad);
-        const unsigned ny = gridDim.y;
-        const unsigned grp = blockIdx.y % kDoneGroups;
-        const unsigned groups = ny < (unsigned)kDoneGroups ? ny : (unsigned)kDoneGroups;
-        const unsigned in_grp = gridDim.x * ((ny - grp + kDoneGroups - 1) / kDoneGroups);
+        unsigned* done = reinterpret_cast<unsigned*>(f.counts + kMaxSegments * kCounterPad);
+        const unsigned gy = f.gy;
+        const unsigned grp = by % kDoneGroups;
+        const unsigned groups = gy < (unsigned)kDoneGroups ? gy : (unsigned)kDoneGroups;
+        const unsigned in_grp = f.gx * ((gy - grp + kDoneGroups - 1) / kDoneGroups);
         int last = 0;
         if (atomicAdd(&done[(1 + grp) * kCounterPad], 1u) == in_grp - 1)
             last = (atomicAdd(&done[0], 1u) == groups - 1) ? 1 : 0;
@@ -255,10 +264,35 @@ __global__ __launch_bounds__(kEdgeThreads) void k_edges_candidates(
     }
     __syncthreads();
     if (s_last) {
-        finish_segments(counts, prefix, n_views * ll.copies);
-        unsigned* done = reinterpret_cast<unsigned*>(counts + kMaxSegments * kCounterPad);
+        finish_frame(f, n_views);
+        unsigned* done = reinterpret_cast<unsigned*>(f.counts + kMaxSegments * kCounterPad);
         for (int i = threadIdx.x; i <= kDoneGroups; i += blockDim.x)
             __hip_atomic_store(&done[i * kCounterPad], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(64 * kMaxEdgeRows) void k_edges(FrameDesc f, int n_views, ViewTable vt,
+                                                               float q_min) {
+    edge_block(f, blockIdx.x, blockIdx.y, n_views, vt, q_min);
+}
+
+// Every frame of a batch: a persistent grid walks the flat list of edge-pass
+// blocks of all frames (frame fi owns [block_begin, next block_begin)).
+__global__ __launch_bounds__(64 * kMaxEdgeRows) void k_edges_batched(
+    const FrameDesc* __restrict__ table, int n_frames, int total_blocks, int n_views, ViewTable vt,
+    float q_min) {
+    int fi = 0;
+    for (int vb = blockIdx.x; vb < total_blocks; vb += gridDim.x) {
+        int lo = fi, hi = n_frames - 1;  // last frame with block_begin <= vb
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (table[mid].block_begin <= vb) lo = mid; else hi = mid - 1;
+        }
+        fi = lo;
+        const FrameDesc& f = table[fi];
+        const int local = vb - f.block_begin;
+        edge_block(f, local % f.gx, local / f.gx, n_views, vt, q_min);
     }
 }
 
@@ -499,59 +533,58 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
     wave_lds_sync();
 }
 
-struct ViewList {
-    int v[OCCL_MAX_VIEWS];
-};
-
-// Flat round-robin over every (view, candidate) pair of the listed views.
-// KMAX = 2 serves the views of register classes K = 1 and 2; larger classes
-// are launched one per class.
 template <int KMAX>
 constexpr int waves_per_block() { return KMAX >= 16 ? 2 : 4; }
 
+// The scanline of candidate `pix` of view v of frame f.
+template <int KMAX>
+__device__ __forceinline__ void scan_item(const FrameDesc& f, int v, uint32_t pix,
+                                          const ViewTable& vt, const Thresholds& th,
+                                          const WaveLds& L, int lane) {
+    const int W = f.W, H = f.H;
+    const int cy = (int)(pix / (uint32_t)W);
+    const int cx = (int)(pix - (uint32_t)cy * (uint32_t)W);
+    const int h = f.h[v];
+    uint8_t* Mv = f.M + (size_t)v * H * W;
+    if constexpr (KMAX == 2) {
+        if (lanes_per_scanline_k(2 * h + 1) == 1)
+            scanline<1>(f.D, H, W, Mv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, th, L, lane);
+        else
+            scanline<2>(f.D, H, W, Mv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, th, L, lane);
+    } else {
+        scanline<KMAX>(f.D, H, W, Mv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, th, L, lane);
+    }
+}
+
+// Segment `lo` (class-local, class-major order) of class cls: its view and
+// its physical segment index.
+__device__ __forceinline__ void segment_of(const FrameDesc& f, int cls, int lo, int* v, int* seg) {
+    const int C = f.ll.copies;
+    *v = f.vord[f.cls_start[cls] + lo / C];
+    *seg = *v * C + lo % C;
+}
+
+// One frame, the views of scan class cls: a flat, chunked walk over every
+// (view, candidate) pair of the class.
 template <int KMAX>
 __global__ __launch_bounds__(64 * waves_per_block<KMAX>()) void k_scanlines(
-    const float* __restrict__ D, int H, int W, uint8_t* __restrict__ M, ViewTable vt,
-    Thresholds th, ViewList vl, int n_list, ListLayout ll, const uint32_t* __restrict__ lists,
-    const int32_t* __restrict__ gpre) {
+    FrameDesc f, int n_views, ViewTable vt, Thresholds th, int cls) {
     constexpr int WPB = waves_per_block<KMAX>();
     constexpr int NT = 64 * WPB;
     __shared__ float lds[WPB][4][64 * KMAX];
     __shared__ uint32_t okeys[WPB][64 * KMAX];
     __shared__ int runs[WPB][kMaxRunsCap + 1];
-    __shared__ int pre[kMaxSegments + 1];  // exclusive prefix over (listed view, copy)
-    __shared__ int vbase[OCCL_MAX_VIEWS + 1];
-    const int C = ll.copies;
-    const int nseg = n_list * C;
-    if (threadIdx.x < 64) {  // per listed view: its candidates and their running sum
-        const int ln = threadIdx.x;
-        int tot = 0;
-        if (ln < n_list) {
-            const int v = vl.v[ln];
-            tot = gpre[(v + 1) * C] - gpre[v * C];
-        }
-        int x = tot;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int y = __shfl_up(x, d, 64);
-            if (ln >= d) x += y;
-        }
-        vbase[ln] = x - tot;
-        if (ln == 63) vbase[64] = x;
-    }
-    __syncthreads();
-    for (int sg = threadIdx.x; sg < nseg; sg += NT) {
-        const int i = sg / C, v = vl.v[i];
-        pre[sg] = vbase[i] + gpre[v * C + sg % C] - gpre[v * C];
-    }
-    if (threadIdx.x == 0) pre[nseg] = vbase[64];
+    __shared__ int pre[kMaxSegments + 1];
+    const int C = f.ll.copies;
+    const int seg0 = f.cls_start[cls] * C;
+    const int nseg = (f.cls_start[cls + 1] - f.cls_start[cls]) * C;
+    const int base = f.prefix[seg0];
+    for (int j = threadIdx.x; j <= nseg; j += NT) pre[j] = f.prefix[seg0 + j] - base;
     __syncthreads();
     const int total = pre[nseg];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const WaveLds L{lds[wave][0], lds[wave][1], okeys[wave], lds[wave][2], lds[wave][3], runs[wave]};
-    // each wavefront takes one contiguous chunk of the flat work list, so the
-    // segment of consecutive items is found by stepping forward
     const int nw = gridDim.x * WPB;
     const int gw = blockIdx.x * WPB + wave;
     const int chunk = (total + nw - 1) / nw;
@@ -567,82 +600,208 @@ __global__ __launch_bounds__(64 * waves_per_block<KMAX>()) void k_scanlines(
     }
     for (int t = gw * chunk; t < t_end; ++t) {
         while (lo + 1 < nseg && pre[lo + 1] <= t) ++lo;
-        const int i = lo / ll.copies;
-        const int v = vl.v[i];
-        const int seg = v * ll.copies + lo % ll.copies;
-        const uint32_t pix = lists[(size_t)seg * ll.cap + (size_t)(t - pre[lo])];
-        const int cy = (int)(pix / (uint32_t)W);
-        const int cx = (int)(pix - (uint32_t)cy * (uint32_t)W);
-        const int h = vt.h[v];
-        uint8_t* Mv = M + (size_t)v * H * W;
-        const int K = lanes_per_scanline_k(2 * h + 1);
-        if constexpr (KMAX == 2) {
-            if (K == 1)
-                scanline<1>(D, H, W, Mv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, th, L, lane);
-            else
-                scanline<2>(D, H, W, Mv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, th, L, lane);
-        } else {
-            scanline<KMAX>(D, H, W, Mv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, th, L, lane);
+        int v, seg;
+        segment_of(f, cls, lo, &v, &seg);
+        const uint32_t pix = f.lists[(size_t)seg * f.ll.cap + (size_t)(t - pre[lo])];
+        scan_item<KMAX>(f, v, pix, vt, th, L, lane);
+    }
+}
+
+// Every frame of a batch, the views of scan class cls: the flat work list
+// is frame-major; frame sizes come from each frame's prefix, segments are
+// located in the frame's prefix in global memory.
+template <int KMAX>
+__global__ __launch_bounds__(64 * waves_per_block<KMAX>()) void k_scanlines_batched(
+    const FrameDesc* __restrict__ table, int n_frames, int n_views, ViewTable vt, Thresholds th,
+    int cls) {
+    constexpr int WPB = waves_per_block<KMAX>();
+    constexpr int NT = 64 * WPB;
+    __shared__ float lds[WPB][4][64 * KMAX];
+    __shared__ uint32_t okeys[WPB][64 * KMAX];
+    __shared__ int runs[WPB][kMaxRunsCap + 1];
+    __shared__ int fpre[kMaxBatch + 1];
+    __shared__ int wsum[WPB];
+    {  // exclusive prefix of the per-frame item counts of this class
+        constexpr int PER = (kMaxBatch + NT - 1) / NT;
+        const int t = threadIdx.x, ln = t & 63, wv = t >> 6;
+        int cnt[PER];
+        int sum = 0;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int fi = t * PER + j;
+            int cc = 0;
+            if (fi < n_frames) {
+                const FrameDesc& f = table[fi];
+                const int C = f.ll.copies;
+                const int s0 = f.cls_start[cls] * C, s1 = f.cls_start[cls + 1] * C;
+                cc = f.prefix[s1] - f.prefix[s0];
+            }
+            cnt[j] = cc;
+            sum += cc;
         }
+        int x = sum;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(x, d, 64);
+            if (ln >= d) x += y;
+        }
+        if (ln == 63) wsum[wv] = x;
+        __syncthreads();
+        int run = x - sum;
+        for (int w = 0; w < wv; ++w) run += wsum[w];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int fi = t * PER + j;
+            if (fi < n_frames) fpre[fi] = run;
+            run += cnt[j];
+        }
+        if (t == NT - 1) fpre[n_frames] = run;
+    }
+    __syncthreads();
+    const int total = fpre[n_frames];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const WaveLds L{lds[wave][0], lds[wave][1], okeys[wave], lds[wave][2], lds[wave][3], runs[wave]};
+    const int nw = gridDim.x * WPB;
+    const int gw = blockIdx.x * WPB + wave;
+    const int chunk = (total + nw - 1) / nw;
+    const int t_end = min(total, (gw + 1) * chunk);
+    int fi = -1, lo = 0, nseg = 0, seg0 = 0, pbase = 0;
+    for (int t = gw * chunk; t < t_end; ++t) {
+        if (fi < 0 || t >= fpre[fi + 1]) {
+            // frame of item t (last with fpre <= t), then its segment by binary search
+            int a = fi < 0 ? 0 : fi, b = n_frames - 1;
+            while (a < b) {
+                const int mid = (a + b + 1) >> 1;
+                if (fpre[mid] <= t) a = mid; else b = mid - 1;
+            }
+            fi = a;
+            const FrameDesc& f = table[fi];
+            const int C = f.ll.copies;
+            seg0 = f.cls_start[cls] * C;
+            nseg = (f.cls_start[cls + 1] - f.cls_start[cls]) * C;
+            pbase = f.prefix[seg0];
+            const int u = t - fpre[fi];
+            int p = 0, q = nseg - 1;
+            while (p < q) {
+                const int mid = (p + q + 1) >> 1;
+                if (f.prefix[seg0 + mid] - pbase <= u) p = mid; else q = mid - 1;
+            }
+            lo = p;
+        }
+        const FrameDesc& f = table[fi];
+        const int u = t - fpre[fi];
+        while (lo + 1 < nseg && f.prefix[seg0 + lo + 1] - pbase <= u) ++lo;
+        int v, seg;
+        segment_of(f, cls, lo, &v, &seg);
+        const uint32_t pix = f.lists[(size_t)seg * f.ll.cap + (size_t)(u - (f.prefix[seg0 + lo] - pbase))];
+        scan_item<KMAX>(f, v, pix, vt, th, L, lane);
     }
 }
 
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// launchers
+// host side
 // ---------------------------------------------------------------------------
-ListLayout make_list_layout(int H, int W, int n_views) {
+ListLayout make_list_layout(int H, int W, int n_views, int edge_rows) {
     ListLayout ll;
-    const int block_rows = (H + kEdgeRows - 1) / kEdgeRows;
+    ll.edge_rows = edge_rows;
+    const int block_rows = (H + edge_rows - 1) / edge_rows;
     int copies = kMaxSegments / (n_views > 0 ? n_views : 1);
     if (copies > kMaxCopies) copies = kMaxCopies;
     if (copies > block_rows) copies = block_rows;
     if (copies < 1) copies = 1;
     ll.block_rows_per_copy = (block_rows + copies - 1) / copies;
     ll.copies = (block_rows + ll.block_rows_per_copy - 1) / ll.block_rows_per_copy;
-    ll.cap = (size_t)ll.block_rows_per_copy * kEdgeRows * (size_t)W;
+    ll.cap = (size_t)ll.block_rows_per_copy * edge_rows * (size_t)W;
     return ll;
 }
 
-hipError_t launch_edges_candidates(hipStream_t st, const float* D, int H, int W, uint8_t* M,
-                                   int n_views, const ViewTable& vt, float q_min,
-                                   const ListLayout& ll, uint32_t* lists, int32_t* counts,
-                                   int32_t* prefix) {
-    const int vec = ((W % 4) == 0 && (reinterpret_cast<uintptr_t>(D) % 16) == 0 &&
-                     (reinterpret_cast<uintptr_t>(M) % 4) == 0)
-                        ? 1
-                        : 0;
-    dim3 grid((W + kEdgeCols - 1) / kEdgeCols, (H + kEdgeRows - 1) / kEdgeRows);
-    hipLaunchKernelGGL(k_edges_candidates, grid, dim3(kEdgeThreads), 0, st, D, H, W, M, n_views,
-                       vt, q_min, ll, lists, counts, prefix, vec);
+void describe_frame(FrameDesc* f, const float* D, uint8_t* M, int H, int W, int n_views,
+                    const int* Ls, int edge_rows) {
+    f->D = D;
+    f->M = M;
+    f->H = H;
+    f->W = W;
+    f->ll = make_list_layout(H, W, n_views, edge_rows);
+    f->gx = (W + kEdgeCols - 1) / kEdgeCols;
+    f->gy = (H + edge_rows - 1) / edge_rows;
+    f->block_begin = 0;
+    for (int v = 0; v < OCCL_MAX_VIEWS; ++v) {
+        f->h[v] = v < n_views ? Ls[v] / 2 : 0;
+        f->vord[v] = 0;
+    }
+    int k = 0;
+    for (int ci = 0; ci < kNumClasses; ++ci) {
+        f->cls_start[ci] = k;
+        for (int v = 0; v < n_views; ++v)
+            if (scan_class(f->h[v]) == ci) f->vord[k++] = v;
+    }
+    f->cls_start[kNumClasses] = k;
+}
+
+hipError_t launch_edges(hipStream_t st, const FrameDesc& f, int n_views, const ViewTable& vt,
+                        float q_min) {
+    hipLaunchKernelGGL(k_edges, dim3(f.gx, f.gy), dim3(64 * f.ll.edge_rows), 0, st, f, n_views, vt,
+                       q_min);
     return hipGetLastError();
 }
 
-hipError_t launch_scanlines(hipStream_t st, const float* D, int H, int W, uint8_t* M,
-                            const ViewTable& vt, const Thresholds& th, const int* views, int n_list,
-                            int kclass, const ListLayout& ll, const uint32_t* lists,
-                            const int32_t* prefix, int n_blocks) {
-    if (n_list <= 0) return hipSuccess;
-    ViewList vl{};
-    for (int i = 0; i < n_list; ++i) vl.v[i] = views[i];
+hipError_t launch_edges_batched(hipStream_t st, const FrameDesc* table, int n_frames,
+                                int total_blocks, int n_views, const ViewTable& vt, float q_min,
+                                int edge_rows, int n_blocks) {
+    hipLaunchKernelGGL(k_edges_batched, dim3(n_blocks), dim3(64 * edge_rows), 0, st, table,
+                       n_frames, total_blocks, n_views, vt, q_min);
+    return hipGetLastError();
+}
+
+hipError_t launch_scanlines(hipStream_t st, const FrameDesc& f, int n_views, const ViewTable& vt,
+                            const Thresholds& th, int cls, int n_blocks) {
     const dim3 grid(n_blocks);
-    switch (kclass) {
+    switch (cls) {
+        case 0:
+            hipLaunchKernelGGL(k_scanlines<2>, grid, dim3(64 * waves_per_block<2>()), 0, st, f,
+                               n_views, vt, th, cls);
+            break;
+        case 1:
+            hipLaunchKernelGGL(k_scanlines<4>, grid, dim3(64 * waves_per_block<4>()), 0, st, f,
+                               n_views, vt, th, cls);
+            break;
         case 2:
-            hipLaunchKernelGGL(k_scanlines<2>, grid, dim3(64 * waves_per_block<2>()), 0, st, D, H, W,
-                               M, vt, th, vl, n_list, ll, lists, prefix);
+            hipLaunchKernelGGL(k_scanlines<8>, grid, dim3(64 * waves_per_block<8>()), 0, st, f,
+                               n_views, vt, th, cls);
             break;
-        case 4:
-            hipLaunchKernelGGL(k_scanlines<4>, grid, dim3(64 * waves_per_block<4>()), 0, st, D, H, W,
-                               M, vt, th, vl, n_list, ll, lists, prefix);
+        case 3:
+            hipLaunchKernelGGL(k_scanlines<16>, grid, dim3(64 * waves_per_block<16>()), 0, st, f,
+                               n_views, vt, th, cls);
             break;
-        case 8:
-            hipLaunchKernelGGL(k_scanlines<8>, grid, dim3(64 * waves_per_block<8>()), 0, st, D, H, W,
-                               M, vt, th, vl, n_list, ll, lists, prefix);
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_scanlines_batched(hipStream_t st, const FrameDesc* table, int n_frames,
+                                    int n_views, const ViewTable& vt, const Thresholds& th,
+                                    int cls, int n_blocks) {
+    const dim3 grid(n_blocks);
+    switch (cls) {
+        case 0:
+            hipLaunchKernelGGL(k_scanlines_batched<2>, grid, dim3(64 * waves_per_block<2>()), 0, st,
+                               table, n_frames, n_views, vt, th, cls);
             break;
-        case 16:
-            hipLaunchKernelGGL(k_scanlines<16>, grid, dim3(64 * waves_per_block<16>()), 0, st, D, H,
-                               W, M, vt, th, vl, n_list, ll, lists, prefix);
+        case 1:
+            hipLaunchKernelGGL(k_scanlines_batched<4>, grid, dim3(64 * waves_per_block<4>()), 0, st,
+                               table, n_frames, n_views, vt, th, cls);
+            break;
+        case 2:
+            hipLaunchKernelGGL(k_scanlines_batched<8>, grid, dim3(64 * waves_per_block<8>()), 0, st,
+                               table, n_frames, n_views, vt, th, cls);
+            break;
+        case 3:
+            hipLaunchKernelGGL(k_scanlines_batched<16>, grid, dim3(64 * waves_per_block<16>()), 0,
+                               st, table, n_frames, n_views, vt, th, cls);
             break;
         default:
             return hipErrorInvalidValue;

@@ -3,6 +3,7 @@
 // Validation, per-view constants (direction vectors, half scan lengths),
 // workspace management and the launch sequence of one frame:
 //   [optional D statistics -> host]  k_edges_candidates  k_scanlines<K> per K.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -110,6 +111,15 @@ occl_ctx::~occl_ctx() {
         (void)hipEventDestroy(p.b);
     }
     for (auto e : ev_pool) (void)hipEventDestroy(e);
+    for (auto& g : graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    graphs.clear();
+    if (table_event) (void)hipEventSynchronize(table_event);
+    if (table_event) (void)hipEventDestroy(table_event);
+    if (table_host) (void)hipHostFree(table_host);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     free_all();
     if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
@@ -137,6 +147,7 @@ occl_status occl_ctx::ensure(const char* name, size_t bytes, void** out) {
         (void)hipFree(b.ptr);
         b.ptr = nullptr;
         b.bytes = 0;
+        drop_graphs();
     }
     size_t alloc = bytes < 256 ? 256 : bytes;
     hipError_t e = hipMalloc(&b.ptr, alloc);
@@ -159,6 +170,14 @@ occl_status occl_ctx::ensure_zeroed(const char* name, size_t bytes, void** out) 
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipMemset(workspace)");
     return OCCL_OK;
+}
+
+void occl_ctx::drop_graphs() {
+    for (auto& g : graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    graphs.clear();
 }
 
 size_t occl_ctx::total_bytes() const {
@@ -196,7 +215,7 @@ extern "C" occl_status occl_init(occl_ctx** out, int device, void* hip_stream,
     void* p;
     occl_status s = ctx->ensure_zeroed("counts", kCountsBytes, &p);
     if (s == OCCL_OK && max_pixels_hint > 0 && max_views_hint > 0)
-        s = ctx->ensure("lists", (max_pixels_hint + (size_t)kMaxCopies * kEdgeRows * 4096) *
+        s = ctx->ensure("lists", (max_pixels_hint + (size_t)kMaxCopies * kMaxEdgeRows * 4096) *
                                      max_views_hint * sizeof(uint32_t), &p);
     if (s != OCCL_OK) {
         delete ctx;
@@ -313,7 +332,6 @@ occl_status occl_ctx::resolve_views(const float* D, int H, int W, int n_views,
         if (Ls[v] > OCCL_MAX_SCAN_LEN) return fail(OCCL_ERR_UNSUPPORTED, "scan length > 1023");
         direction_of(angles[v], &vt->c[v], &vt->s[v]);
         vt->r[v] = ratios[v];
-        vt->h[v] = Ls[v] / 2;
     }
     return OCCL_OK;
 }
@@ -396,40 +414,39 @@ extern "C" occl_status occl_profile_read(occl_ctx* ctx, double* ms, int64_t* lau
     return OCCL_OK;
 }
 
-// Enqueues the exact path of one frame.
-occl_status occl_ctx::enqueue_frame(const float* D, int H, int W, int n_views, const ViewTable& vt,
-                                    const Thresholds& th, uint8_t* M) {
-    const ListLayout ll = make_list_layout(H, W, n_views);
+// Enqueues the exact path of one frame (launch shape: cfg, else the tuned or
+// default shape for this frame).
+occl_status occl_ctx::enqueue_frame(const float* D, int H, int W, int n_views, const int* Ls,
+                                    const ViewTable& vt, const Thresholds& th, uint8_t* M,
+                                    const TuneConfig* cfg) {
+    int maxcls = 0;
+    for (int v = 0; v < n_views; ++v) maxcls = std::max(maxcls, scan_class(Ls[v] / 2));
+    const TuneConfig tc = cfg ? *cfg : config_for(tune_key(false, (size_t)H * W, n_views, maxcls));
+    FrameDesc f;
+    describe_frame(&f, D, M, H, W, n_views, Ls, tc.edge_rows);
     void *lists, *counts, *prefix;
-    occl_status s = ensure("lists", ll.cap * ll.copies * n_views * sizeof(uint32_t), &lists);
+    occl_status s = ensure("lists", f.ll.cap * f.ll.copies * n_views * sizeof(uint32_t), &lists);
     if (s != OCCL_OK) return s;
     s = ensure_zeroed("counts", kCountsBytes, &counts);
     if (s != OCCL_OK) return s;
-    s = ensure("prefix", (kMaxSegments + 1) * sizeof(int32_t), &prefix);
+    s = ensure("prefix", kPrefixInts * sizeof(int32_t), &prefix);
     if (s != OCCL_OK) return s;
+    f.lists = (uint32_t*)lists;
+    f.counts = (int32_t*)counts;
+    f.prefix = (int32_t*)prefix;
     hipEvent_t ev = prof_begin(OCCL_STAGE_EDGES);
-    hipError_t e = launch_edges_candidates(stream, D, H, W, M, n_views, vt, th.q_min, ll,
-                                           (uint32_t*)lists, (int32_t*)counts, (int32_t*)prefix);
-    if (e != hipSuccess) return hip_fail(e, "edges_candidates");
+    hipError_t e = launch_edges(stream, f, n_views, vt, th.q_min);
+    if (e != hipSuccess) return hip_fail(e, "edges");
     prof_end(OCCL_STAGE_EDGES, ev);
     ev = prof_begin(OCCL_STAGE_SCANLINES);
-    // one scanline launch per register class: K <= 2 together, then 4, 8, 16
-    const int kclasses[4] = {2, 4, 8, 16};
-    for (int ci = 0; ci < 4; ++ci) {
-        int list[OCCL_MAX_VIEWS];
-        int nl = 0;
-        for (int v = 0; v < n_views; ++v) {
-            const int K = lanes_per_scanline_k(2 * vt.h[v] + 1);
-            if ((K <= 2 ? 2 : K) == kclasses[ci]) list[nl++] = v;
-        }
-        if (!nl) continue;
-        e = launch_scanlines(stream, D, H, W, M, vt, th, list, nl, kclasses[ci], ll,
-                             (const uint32_t*)lists, (const int32_t*)prefix, 8 * n_cu);
+    // one scanline launch per register class present: K <= 2, then 4, 8, 16
+    for (int ci = 0; ci < kNumClasses; ++ci) {
+        if (f.cls_start[ci + 1] == f.cls_start[ci]) continue;
+        e = launch_scanlines(stream, f, n_views, vt, th, ci, tc.scan_blocks_per_cu * n_cu);
         if (e != hipSuccess) return hip_fail(e, "scanlines");
     }
     prof_end(OCCL_STAGE_SCANLINES, ev);
-    last_H = H;
-    last_W = W;
+    last_frame = f;
     last_views = n_views;
     return OCCL_OK;
 }
@@ -464,8 +481,7 @@ extern "C" occl_status occl_detect(occl_ctx* ctx, const float* D, int32_t H, int
     if ((size_t)H * (size_t)W > (size_t)1 << 31) return ctx->fail(OCCL_ERR_UNSUPPORTED, "frame too large");
     if ((size_t)H * W == 0 || n_views == 0) return OCCL_OK;
     if (!D || !M) return ctx->fail(OCCL_ERR_INVALID_ARG, "D or M is NULL");
-    if (H > 65535 * kEdgeRows || W > 65535 * kEdgeCols)
-        return ctx->fail(OCCL_ERR_UNSUPPORTED, "frame too large");
+    if (H > 65535 || W > 65535 * kEdgeCols) return ctx->fail(OCCL_ERR_UNSUPPORTED, "frame too large");
     if ((params->flags & OCCL_FLAG_USE_CNN) && !ctx->cnn_ready())
         return ctx->fail(OCCL_ERR_NO_MODEL, "USE_CNN without loaded weights");
     hipError_t e = hipSetDevice(ctx->device);
@@ -476,9 +492,9 @@ extern "C" occl_status occl_detect(occl_ctx* ctx, const float* D, int32_t H, int
     if (s != OCCL_OK) return s;
     const Thresholds th = make_thresholds(params);
     if (params->flags & OCCL_FLAG_USE_CNN)
-        s = ctx->enqueue_frame_cnn(D, H, W, n_views, vt, th, params, M);
+        s = ctx->enqueue_frame_cnn(D, H, W, n_views, Ls, vt, th, params, M);
     else
-        s = ctx->enqueue_frame(D, H, W, n_views, vt, th, M);
+        s = ctx->enqueue_frame(D, H, W, n_views, Ls, vt, th, M, nullptr);
     if (s != OCCL_OK) return s;
     if (params->flags & OCCL_FLAG_SYNC) {
         e = hipStreamSynchronize(ctx->stream);
@@ -492,16 +508,15 @@ extern "C" occl_status occl_last_candidate_counts(occl_ctx* ctx, int64_t* out, i
     if (ctx->last_views <= 0 || n_views != ctx->last_views)
         return ctx->fail(OCCL_ERR_STATE, "no matching previous occl_detect");
     (void)hipSetDevice(ctx->device);
-    const ListLayout ll = make_list_layout(ctx->last_H, ctx->last_W, n_views);
-    std::vector<int32_t> h((size_t)n_views * ll.copies + 1);
-    auto it = ctx->bufs.find("prefix");
-    if (it == ctx->bufs.end()) return ctx->fail(OCCL_ERR_STATE, "no prefix");
+    const FrameDesc& f = ctx->last_frame;
+    const int C = f.ll.copies;
+    std::vector<int32_t> h((size_t)n_views * C + 1);
     hipError_t e = hipStreamSynchronize(ctx->stream);
     if (e == hipSuccess)
-        e = hipMemcpy(h.data(), it->second.ptr, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
+        e = hipMemcpy(h.data(), f.prefix, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return ctx->hip_fail(e, "prefix readback");
-    for (int v = 0; v < n_views; ++v)
-        out[v] = (int64_t)h[(size_t)(v + 1) * ll.copies] - h[(size_t)v * ll.copies];
+    for (int k = 0; k < n_views; ++k)  // prefix runs over views in vord order
+        out[f.vord[k]] = (int64_t)h[(size_t)(k + 1) * C] - h[(size_t)k * C];
     return OCCL_OK;
 }
 

@@ -1,4 +1,19 @@
-// occl_batch.hip -- occl_detect_batched: many frames of uneven size.
+// occl_batch.hip -- many frames of uneven size in one graph launch, and the
+// launch-shape autotuner.
+//
+// A batch is described to the kernels by a table of FrameDesc entries in
+// device memory (uploaded from pinned host memory on the context's stream
+// before every launch).  The edge pass and the scanline pass of all frames
+// run as two persistent kernels (one more per extra scan class present);
+// the pair is captured once into a hipGraph on a private capture stream and
+// replayed with hipGraphLaunch on the context's stream for every later batch
+// with the same signature (table address, frame count, launch shape,
+// thresholds and views).  Frame pointers and sizes live in the table, not
+// in the graph, so new frames of the same shapes reuse the graph.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
 #include <vector>
 
 #include "occl_ctx.h"
@@ -6,10 +21,156 @@
 
 using namespace occl;
 
-extern "C" occl_status occl_detect_batched(occl_ctx* ctx, int32_t n_frames, const occl_frame* frames,
-                                           int32_t n_views, const double* angles_deg,
-                                           const float* ratios, const occl_params* params) {
-    if (!ctx) return OCCL_ERR_INVALID_ARG;
+namespace {
+
+struct BatchSig {
+    const void* table;
+    int n_frames, total_blocks, n_views, edge_rows, edge_grid, scan_grid;
+    unsigned cls_mask;
+    Thresholds th;
+    ViewTable vt;
+};
+
+std::vector<uint8_t> sig_bytes(const BatchSig& s) {
+    std::vector<uint8_t> b(sizeof(BatchSig));
+    std::memcpy(b.data(), &s, sizeof(BatchSig));
+    return b;
+}
+
+}  // namespace
+
+occl_status occl_ctx::enqueue_batch(int n_frames, const occl_frame* frames, int n_views,
+                                    const int* Ls_all, const ViewTable& vt, const Thresholds& th,
+                                    const TuneConfig* cfg) {
+    size_t px = 0;
+    int maxcls = 0;
+    for (int f = 0; f < n_frames; ++f) {
+        px += (size_t)frames[f].H * frames[f].W;
+        for (int v = 0; v < n_views; ++v) maxcls = std::max(maxcls, scan_class(Ls_all[f * n_views + v] / 2));
+    }
+    const TuneConfig tc = cfg ? *cfg : config_for(tune_key(true, px, n_views, maxcls));
+    hipError_t e;
+    if (!table_host) {
+        e = hipHostMalloc((void**)&table_host, kMaxBatch * sizeof(FrameDesc), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            table_host = nullptr;
+            return hip_fail(e, "hipHostMalloc(frame table)");
+        }
+        e = hipEventCreateWithFlags(&table_event, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    } else {
+        e = hipEventSynchronize(table_event);  // the previous upload has left the staging area
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize(table)");
+    }
+    size_t lists_total = 0;
+    int total_blocks = 0;
+    unsigned cls_mask = 0;
+    std::vector<size_t> lists_off(n_frames);
+    for (int f = 0; f < n_frames; ++f) {
+        FrameDesc& d = table_host[f];
+        describe_frame(&d, frames[f].D, frames[f].M, frames[f].H, frames[f].W, n_views,
+                       Ls_all + (size_t)f * n_views, tc.edge_rows);
+        d.block_begin = total_blocks;
+        total_blocks += d.gx * d.gy;
+        lists_off[f] = lists_total;
+        lists_total += d.ll.cap * d.ll.copies * n_views;
+        for (int ci = 0; ci < kNumClasses; ++ci)
+            if (d.cls_start[ci + 1] > d.cls_start[ci]) cls_mask |= 1u << ci;
+    }
+    void *lists, *counts, *prefix, *table;
+    occl_status s = ensure("blists", std::max<size_t>(lists_total, 1) * sizeof(uint32_t), &lists);
+    if (s == OCCL_OK) s = ensure_zeroed("bcounts", (size_t)n_frames * kCountsBytes, &counts);
+    if (s == OCCL_OK) s = ensure("bprefix", (size_t)n_frames * kPrefixInts * sizeof(int32_t), &prefix);
+    if (s == OCCL_OK) s = ensure("btable", (size_t)n_frames * sizeof(FrameDesc), &table);
+    if (s != OCCL_OK) return s;
+    for (int f = 0; f < n_frames; ++f) {
+        FrameDesc& d = table_host[f];
+        d.lists = (uint32_t*)lists + lists_off[f];
+        d.counts = (int32_t*)counts + (size_t)f * kCountsInts;
+        d.prefix = (int32_t*)prefix + (size_t)f * kPrefixInts;
+    }
+    e = hipMemcpyAsync(table, table_host, (size_t)n_frames * sizeof(FrameDesc),
+                       hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipEventRecord(table_event, stream);
+    if (e != hipSuccess) return hip_fail(e, "frame table upload");
+
+    BatchSig sg;
+    std::memset(&sg, 0, sizeof(sg));
+    sg.table = table;
+    sg.n_frames = n_frames;
+    sg.total_blocks = total_blocks;
+    sg.n_views = n_views;
+    sg.edge_rows = tc.edge_rows;
+    sg.edge_grid = std::min(total_blocks, n_cu * std::max(1, 32 / tc.edge_rows));
+    sg.scan_grid = tc.scan_blocks_per_cu * n_cu;
+    sg.cls_mask = cls_mask;
+    sg.th = th;
+    sg.vt = vt;
+    const std::vector<uint8_t> key = sig_bytes(sg);
+    hipGraphExec_t exec = nullptr;
+    for (size_t i = 0; i < graphs.size(); ++i) {
+        if (graphs[i].sig == key) {
+            exec = graphs[i].exec;
+            std::rotate(graphs.begin(), graphs.begin() + i, graphs.begin() + i + 1);
+            break;
+        }
+    }
+    if (!exec) {
+        if (!cap_stream) {
+            e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
+            if (e != hipSuccess) {
+                cap_stream = nullptr;
+                return hip_fail(e, "hipStreamCreate(capture)");
+            }
+        }
+        e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        hipError_t le = launch_edges_batched(cap_stream, (const FrameDesc*)table, n_frames,
+                                             total_blocks, n_views, vt, th.q_min, tc.edge_rows,
+                                             sg.edge_grid);
+        for (int ci = 0; ci < kNumClasses && le == hipSuccess; ++ci)
+            if (cls_mask & (1u << ci))
+                le = launch_scanlines_batched(cap_stream, (const FrameDesc*)table, n_frames, n_views,
+                                              vt, th, ci, sg.scan_grid);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(cap_stream, &graph);
+        if (le != hipSuccess || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return hip_fail(le != hipSuccess ? le : e, "batch capture");
+        }
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        GraphEntry g;
+        g.sig = key;
+        g.graph = graph;
+        g.exec = exec;
+        graphs.insert(graphs.begin(), std::move(g));
+        while (graphs.size() > 4) {
+            (void)hipGraphExecDestroy(graphs.back().exec);
+            (void)hipGraphDestroy(graphs.back().graph);
+            graphs.pop_back();
+        }
+        ++graph_builds;
+    }
+    hipEvent_t ev = prof_begin(OCCL_STAGE_BATCHED);
+    e = hipGraphLaunch(exec, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    prof_end(OCCL_STAGE_BATCHED, ev);
+    ++graph_launches;
+    return OCCL_OK;
+}
+
+namespace {
+
+// Validation and per-frame scan lengths of a batch call; fills the compacted
+// list of non-empty frames and their L values.
+occl_status prepare_batch(occl_ctx* ctx, int32_t n_frames, const occl_frame* frames,
+                          int32_t n_views, const double* angles_deg, const float* ratios,
+                          const occl_params* params, std::vector<occl_frame>* live,
+                          std::vector<int>* Ls_all, ViewTable* vt) {
     if (n_frames < 0 || (n_frames > 0 && !frames)) return ctx->fail(OCCL_ERR_INVALID_ARG, "frames");
     occl_status s = ctx->check_params(params, n_views, angles_deg, ratios);
     if (s != OCCL_OK) return s;
@@ -17,35 +178,226 @@ extern "C" occl_status occl_detect_batched(occl_ctx* ctx, int32_t n_frames, cons
     for (int f = 0; f < n_frames; ++f) {
         const occl_frame& fr = frames[f];
         if (fr.H < 0 || fr.W < 0) return ctx->fail(OCCL_ERR_INVALID_ARG, "negative frame size");
+        if (fr.H > 65535 || fr.W > 65535 * kEdgeCols || (size_t)fr.H * fr.W > ((size_t)1 << 31))
+            return ctx->fail(OCCL_ERR_UNSUPPORTED, "frame too large");
         if ((size_t)fr.H * fr.W > 0 && n_views > 0 && (!fr.D || !fr.M))
             return ctx->fail(OCCL_ERR_INVALID_ARG, "frame D or M is NULL");
         if (fr.scan_len_per_view)
             for (int v = 0; v < n_views; ++v)
                 if (fr.scan_len_per_view[v] < 1) return ctx->fail(OCCL_ERR_INVALID_ARG, "frame L < 1");
     }
-    if (n_frames == 0 || n_views == 0) return OCCL_OK;
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return ctx->hip_fail(e, "hipSetDevice");
-    const Thresholds th = make_thresholds(params);
+    live->clear();
+    Ls_all->clear();
+    if (n_views == 0) return OCCL_OK;
     for (int f = 0; f < n_frames; ++f) {
         const occl_frame& fr = frames[f];
         if ((size_t)fr.H * fr.W == 0) continue;
-        ViewTable vt{};
         int Ls[OCCL_MAX_VIEWS];
         s = ctx->resolve_views(fr.D, fr.H, fr.W, n_views, angles_deg, ratios, params,
-                               fr.scan_len_per_view, &vt, Ls);
+                               fr.scan_len_per_view, vt, Ls);
         if (s != OCCL_OK) return s;
-        s = ctx->enqueue_frame(fr.D, fr.H, fr.W, n_views, vt, th, fr.M);
+        live->push_back(fr);
+        Ls_all->insert(Ls_all->end(), Ls, Ls + n_views);
+    }
+    return OCCL_OK;
+}
+
+occl_status run_batch(occl_ctx* ctx, const std::vector<occl_frame>& live, const std::vector<int>& Ls,
+                      int n_views, const ViewTable& vt, const Thresholds& th, const TuneConfig* cfg) {
+    for (size_t f0 = 0; f0 < live.size(); f0 += kMaxBatch) {
+        const int n = (int)std::min<size_t>(kMaxBatch, live.size() - f0);
+        occl_status s = ctx->enqueue_batch(n, live.data() + f0, n_views, Ls.data() + f0 * n_views, vt,
+                                           th, cfg);
         if (s != OCCL_OK) return s;
     }
+    return OCCL_OK;
+}
+
+}  // namespace
+
+extern "C" occl_status occl_detect_batched(occl_ctx* ctx, int32_t n_frames, const occl_frame* frames,
+                                           int32_t n_views, const double* angles_deg,
+                                           const float* ratios, const occl_params* params) {
+    if (!ctx) return OCCL_ERR_INVALID_ARG;
+    std::vector<occl_frame> live;
+    std::vector<int> Ls;
+    ViewTable vt{};
+    occl_status s = prepare_batch(ctx, n_frames, frames, n_views, angles_deg, ratios, params, &live,
+                                  &Ls, &vt);
+    if (s != OCCL_OK || live.empty()) return s;
+    s = run_batch(ctx, live, Ls, n_views, vt, make_thresholds(params), nullptr);
+    if (s != OCCL_OK) return s;
     if (params->flags & OCCL_FLAG_SYNC) {
-        e = hipStreamSynchronize(ctx->stream);
+        hipError_t e = hipStreamSynchronize(ctx->stream);
         if (e != hipSuccess) return ctx->hip_fail(e, "hipStreamSynchronize");
     }
     return OCCL_OK;
 }
 
-occl_status occl_ctx::enqueue_frame_cnn(const float*, int, int, int, const ViewTable&,
+occl_status occl_ctx::enqueue_frame_cnn(const float*, int, int, int, const int*, const ViewTable&,
                                         const Thresholds&, const occl_params*, uint8_t*) {
     return fail(OCCL_ERR_NO_MODEL, "learned tile proposal not loaded");
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: coordinate search over the launch shape, timed with HIP events
+// on the context's stream on the caller's own data
+// ---------------------------------------------------------------------------
+namespace {
+
+const int kEdgeRowsCand[] = {1, 2, 4, 8, 16};
+const int kScanBpcCand[] = {2, 4, 8, 16};
+
+template <class F>
+occl_status time_config(occl_ctx* ctx, F&& enqueue, int reps, float* ms) {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e != hipSuccess) return ctx->hip_fail(e, "hipEventCreate(tune)");
+    occl_status s = OCCL_OK;
+    for (int i = 0; i < 2 && s == OCCL_OK; ++i) s = enqueue();
+    if (s == OCCL_OK) e = hipEventRecord(a, ctx->stream);
+    for (int i = 0; i < reps && s == OCCL_OK && e == hipSuccess; ++i) s = enqueue();
+    if (s == OCCL_OK && e == hipSuccess) e = hipEventRecord(b, ctx->stream);
+    if (s == OCCL_OK && e == hipSuccess) e = hipEventSynchronize(b);
+    float t = 0.0f;
+    if (s == OCCL_OK && e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (s != OCCL_OK) return s;
+    if (e != hipSuccess) return ctx->hip_fail(e, "tune timing");
+    *ms = t / reps;
+    return OCCL_OK;
+}
+
+template <class F>
+occl_status search(occl_ctx* ctx, F&& enqueue_with, int reps, TuneConfig* best, float* best_ms) {
+    *best = ctx->tune_default;
+    *best_ms = INFINITY;
+    for (int er : kEdgeRowsCand) {
+        TuneConfig c{er, best->scan_blocks_per_cu};
+        float ms;
+        occl_status s = time_config(ctx, [&] { return enqueue_with(c); }, reps, &ms);
+        if (s != OCCL_OK) return s;
+        if (ms < *best_ms) {
+            *best_ms = ms;
+            *best = c;
+        }
+    }
+    for (int bpc : kScanBpcCand) {
+        TuneConfig c{best->edge_rows, bpc};
+        float ms;
+        occl_status s = time_config(ctx, [&] { return enqueue_with(c); }, reps, &ms);
+        if (s != OCCL_OK) return s;
+        if (ms < *best_ms) {
+            *best_ms = ms;
+            *best = c;
+        }
+    }
+    return OCCL_OK;
+}
+
+}  // namespace
+
+extern "C" occl_status occl_autotune(occl_ctx* ctx, const float* D, int32_t H, int32_t W,
+                                     int32_t n_views, const double* angles_deg, const float* ratios,
+                                     const occl_params* params, uint8_t* M, int32_t reps,
+                                     occl_tune* out) {
+    if (!ctx) return OCCL_ERR_INVALID_ARG;
+    occl_status s = ctx->check_params(params, n_views, angles_deg, ratios);
+    if (s != OCCL_OK) return s;
+    if (H < 1 || W < 1 || n_views < 1 || !D || !M) return ctx->fail(OCCL_ERR_INVALID_ARG, "frame");
+    if (H > 65535 || W > 65535 * kEdgeCols || (size_t)H * W > ((size_t)1 << 31))
+        return ctx->fail(OCCL_ERR_UNSUPPORTED, "frame too large");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return ctx->hip_fail(e, "hipSetDevice");
+    ViewTable vt{};
+    int Ls[OCCL_MAX_VIEWS];
+    s = ctx->resolve_views(D, H, W, n_views, angles_deg, ratios, params, nullptr, &vt, Ls);
+    if (s != OCCL_OK) return s;
+    const Thresholds th = make_thresholds(params);
+    TuneConfig best;
+    float best_ms;
+    s = search(ctx, [&](const TuneConfig& c) { return ctx->enqueue_frame(D, H, W, n_views, Ls, vt, th, M, &c); },
+               reps > 0 ? reps : 10, &best, &best_ms);
+    if (s != OCCL_OK) return s;
+    int maxcls = 0;
+    for (int v = 0; v < n_views; ++v) maxcls = std::max(maxcls, scan_class(Ls[v] / 2));
+    ctx->tuned[tune_key(false, (size_t)H * W, n_views, maxcls)] = best;
+    if (out) {
+        out->edge_rows = best.edge_rows;
+        out->scan_blocks_per_cu = best.scan_blocks_per_cu;
+        out->ms = best_ms;
+    }
+    return OCCL_OK;
+}
+
+extern "C" occl_status occl_autotune_batched(occl_ctx* ctx, int32_t n_frames, const occl_frame* frames,
+                                             int32_t n_views, const double* angles_deg,
+                                             const float* ratios, const occl_params* params,
+                                             int32_t reps, occl_tune* out) {
+    if (!ctx) return OCCL_ERR_INVALID_ARG;
+    std::vector<occl_frame> live;
+    std::vector<int> Ls;
+    ViewTable vt{};
+    occl_status s = prepare_batch(ctx, n_frames, frames, n_views, angles_deg, ratios, params, &live,
+                                  &Ls, &vt);
+    if (s != OCCL_OK) return s;
+    if (live.empty() || (int)live.size() > kMaxBatch)
+        return ctx->fail(OCCL_ERR_INVALID_ARG, "autotune needs 1..1024 non-empty frames");
+    const Thresholds th = make_thresholds(params);
+    TuneConfig best;
+    float best_ms;
+    s = search(ctx, [&](const TuneConfig& c) { return run_batch(ctx, live, Ls, n_views, vt, th, &c); },
+               reps > 0 ? reps : 5, &best, &best_ms);
+    if (s != OCCL_OK) return s;
+    size_t px = 0;
+    int maxcls = 0;
+    for (size_t f = 0; f < live.size(); ++f) {
+        px += (size_t)live[f].H * live[f].W;
+        for (int v = 0; v < n_views; ++v) maxcls = std::max(maxcls, scan_class(Ls[f * n_views + v] / 2));
+    }
+    ctx->tuned[tune_key(true, px, n_views, maxcls)] = best;
+    if (out) {
+        out->edge_rows = best.edge_rows;
+        out->scan_blocks_per_cu = best.scan_blocks_per_cu;
+        out->ms = best_ms;
+    }
+    return OCCL_OK;
+}
+
+extern "C" occl_status occl_tune_save(const occl_ctx* ctx, const char* path) {
+    if (!ctx || !path) return OCCL_ERR_INVALID_ARG;
+    FILE* fp = std::fopen(path, "w");
+    if (!fp) return OCCL_ERR_INVALID_ARG;
+    std::fprintf(fp, "# occl launch shapes: bucket edge_rows scan_blocks_per_cu\n");
+    for (const auto& kv : ctx->tuned)
+        std::fprintf(fp, "%llu %d %d\n", (unsigned long long)kv.first, kv.second.edge_rows,
+                     kv.second.scan_blocks_per_cu);
+    const bool ok = std::fclose(fp) == 0;
+    return ok ? OCCL_OK : OCCL_ERR_INVALID_ARG;
+}
+
+extern "C" occl_status occl_tune_load(occl_ctx* ctx, const char* path) {
+    if (!ctx || !path) return OCCL_ERR_INVALID_ARG;
+    FILE* fp = std::fopen(path, "r");
+    if (!fp) return ctx->fail(OCCL_ERR_INVALID_ARG, "cannot open tune file");
+    char line[256];
+    std::map<uint64_t, TuneConfig> got;
+    while (std::fgets(line, sizeof(line), fp)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        unsigned long long k;
+        int er, bpc;
+        if (std::sscanf(line, "%llu %d %d", &k, &er, &bpc) != 3 || er < 1 || er > kMaxEdgeRows ||
+            (er & (er - 1)) != 0 || bpc < 1 || bpc > 64) {
+            std::fclose(fp);
+            return ctx->fail(OCCL_ERR_INVALID_ARG, "malformed tune file");
+        }
+        got[(uint64_t)k] = TuneConfig{er, bpc};
+    }
+    std::fclose(fp);
+    for (const auto& kv : got) ctx->tuned[kv.first] = kv.second;
+    return OCCL_OK;
 }

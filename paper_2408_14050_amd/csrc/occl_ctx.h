@@ -3,12 +3,22 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
 #include <map>
 #include <string>
 #include <vector>
 
 #include "occl.h"
 #include "occl_internal.h"
+
+// Tuning bucket of a launch: batched or not, frame size class (log2 of the
+// pixels), view count and the largest scan class.
+inline uint64_t tune_key(bool batched, size_t pixels, int n_views, int max_class) {
+    int lg = 0;
+    while (lg < 62 && ((size_t)1 << (lg + 1)) <= pixels) ++lg;
+    return (uint64_t)(batched ? 1 : 0) | ((uint64_t)lg << 1) | ((uint64_t)n_views << 8) |
+           ((uint64_t)max_class << 16);
+}
 
 struct occl_ctx {
     struct Buf {
@@ -24,7 +34,28 @@ struct occl_ctx {
     size_t workspace_cap = 0;            // 0 = unlimited
     uint32_t* host_stats = nullptr;      // pinned 64-byte staging area for read-backs
     std::string last_error;
-    int last_H = 0, last_W = 0, last_views = 0;
+    int last_views = 0;
+    occl::FrameDesc last_frame{};        // layout of the most recent single-frame call
+
+    // launch shapes: tuned per bucket (tune_key), default otherwise
+    std::map<uint64_t, occl::TuneConfig> tuned;
+    occl::TuneConfig tune_default{4, 8};
+    occl::TuneConfig config_for(uint64_t key) const {
+        auto it = tuned.find(key);
+        return it == tuned.end() ? tune_default : it->second;
+    }
+
+    // batched path: frame table staging, graph cache, capture stream
+    occl::FrameDesc* table_host = nullptr;  // pinned, kMaxBatch entries
+    hipEvent_t table_event = nullptr;       // last upload from table_host
+    hipStream_t cap_stream = nullptr;       // graphs are captured here (never the null stream)
+    struct GraphEntry {
+        std::vector<uint8_t> sig;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<GraphEntry> graphs;         // most recent first
+    int64_t graph_builds = 0, graph_launches = 0;
 
     // learned tile proposal (k_cnn.hip); weights live in `bufs`
     bool cnn_loaded = false;
@@ -37,8 +68,8 @@ struct occl_ctx {
     bool profiling = false;
     std::vector<EvPair> ev_pairs;     // recorded, not yet resolved
     std::vector<hipEvent_t> ev_pool;  // free events
-    double prof_ms[OCCL_N_STAGES] = {0, 0, 0, 0};
-    int64_t prof_n[OCCL_N_STAGES] = {0, 0, 0, 0};
+    double prof_ms[OCCL_N_STAGES] = {};
+    int64_t prof_n[OCCL_N_STAGES] = {};
     hipEvent_t prof_begin(int stage);        // records and returns the start event (or null)
     void prof_end(int stage, hipEvent_t a);  // records the end event
     occl_status prof_resolve();
@@ -46,6 +77,7 @@ struct occl_ctx {
 
     ~occl_ctx();
     void free_all();
+    void drop_graphs();
     size_t total_bytes() const;
     occl_status ensure(const char* name, size_t bytes, void** out);
     occl_status ensure_zeroed(const char* name, size_t bytes, void** out);
@@ -58,11 +90,15 @@ struct occl_ctx {
     occl_status resolve_views(const float* D, int H, int W, int n_views, const double* angles,
                               const float* ratios, const occl_params* p, const int32_t* frame_L,
                               occl::ViewTable* vt, int* Ls);
-    occl_status enqueue_frame(const float* D, int H, int W, int n_views, const occl::ViewTable& vt,
-                              const occl::Thresholds& th, uint8_t* M);
+    occl_status enqueue_frame(const float* D, int H, int W, int n_views, const int* Ls,
+                              const occl::ViewTable& vt, const occl::Thresholds& th, uint8_t* M,
+                              const occl::TuneConfig* cfg);
+    occl_status enqueue_batch(int n_frames, const occl_frame* frames, int n_views, const int* Ls_all,
+                              const occl::ViewTable& vt, const occl::Thresholds& th,
+                              const occl::TuneConfig* cfg);
 
     bool cnn_ready() const { return cnn_loaded; }
-    occl_status enqueue_frame_cnn(const float* D, int H, int W, int n_views,
+    occl_status enqueue_frame_cnn(const float* D, int H, int W, int n_views, const int* Ls,
                                   const occl::ViewTable& vt, const occl::Thresholds& th,
                                   const occl_params* p, uint8_t* M);
 };

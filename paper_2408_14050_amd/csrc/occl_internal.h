@@ -11,11 +11,11 @@
 
 namespace occl {
 
-// Edge pass block: 4 wavefronts, one 256-pixel row segment each (64 lanes x 4
-// pixels), on 4 consecutive rows.
+// Edge pass: one wavefront per 256-pixel row segment (64 lanes x 4 pixels);
+// a block stacks `edge_rows` (1..kMaxEdgeRows, tuned) wavefronts on
+// consecutive rows.
 constexpr int kEdgeCols = 256;
-constexpr int kEdgeRows = 4;
-constexpr int kEdgeThreads = 256;
+constexpr int kMaxEdgeRows = 16;
 
 // Candidate lists.  The candidates of a view are split into `copies`
 // segments by horizontal bands of edge-pass block rows; each segment has its
@@ -26,27 +26,37 @@ constexpr int kEdgeThreads = 256;
 constexpr int kCounterPad = 32;    // int32 stride between counters (128 bytes)
 constexpr int kMaxCopies = 64;
 constexpr int kMaxSegments = 1024; // views x copies
-// "counts" workspace: kMaxSegments padded counters, then the edge pass's
-// completion counters (one top counter and kDoneGroups group counters); all
-// are zero between frames.
+// Per-frame "counts" workspace: kMaxSegments padded counters, then the edge
+// pass's completion counters (one top counter and kDoneGroups group
+// counters); all are zero between frames.
 constexpr int kDoneGroups = 32;
-constexpr size_t kCountsBytes =
-    ((size_t)kMaxSegments + 1 + kDoneGroups) * kCounterPad * sizeof(int32_t);
+constexpr size_t kCountsInts = ((size_t)kMaxSegments + 1 + kDoneGroups) * kCounterPad;
+constexpr size_t kCountsBytes = kCountsInts * sizeof(int32_t);
+constexpr size_t kPrefixInts = kMaxSegments + 1;
 
-struct ListLayout {
-    int copies;               // segments per view
-    int block_rows_per_copy;  // edge-pass block rows feeding one segment
-    size_t cap;               // entries per segment
-};
-ListLayout make_list_layout(int H, int W, int n_views);
+// Scanline register classes: a scanline of n samples keeps K = 1, 2, 4, 8 or
+// 16 samples per lane; class 0 serves K = 1 and 2, classes 1..3 serve 4, 8, 16.
+constexpr int kNumClasses = 4;
+constexpr int kMaxBatch = 1024;
 
-// Per-view constants, passed by value as a kernel argument (copied at
-// launch, so nothing on the host has to outlive the call).
+// Smallest K (power of two, 1..16) with 64*K >= n samples.
+__host__ __device__ inline int lanes_per_scanline_k(int n) {
+    int k = 1;
+    while (64 * k < n) k <<= 1;
+    return k;
+}
+__host__ __device__ inline int scan_class(int h) {
+    const int K = lanes_per_scanline_k(2 * h + 1);
+    return K <= 2 ? 0 : (K == 4 ? 1 : (K == 8 ? 2 : 3));
+}
+
+// Per-view constants shared by every frame of a call, passed by value as a
+// kernel argument (copied at launch, so nothing on the host has to outlive
+// the call).
 struct ViewTable {
     float c[OCCL_MAX_VIEWS];   // cos(alpha), fp32 (octant-exact rule)
     float s[OCCL_MAX_VIEWS];   // sin(alpha)
     float r[OCCL_MAX_VIEWS];   // baseline ratio
-    int h[OCCL_MAX_VIEWS];     // half scan length floor(L/2)
 };
 
 struct Thresholds {
@@ -57,18 +67,54 @@ struct Thresholds {
     int ns;        // neighbours per side, max(1, ceil(N/2))
 };
 
-// Smallest K (power of two, 1..16) with 64*K >= n samples.
-__host__ __device__ inline int lanes_per_scanline_k(int n) {
-    int k = 1;
-    while (64 * k < n) k <<= 1;
-    return k;
-}
+struct ListLayout {
+    int copies;               // segments per view
+    int block_rows_per_copy;  // edge-pass block rows feeding one segment
+    int edge_rows;            // rows (wavefronts) per edge-pass block
+    size_t cap;               // entries per segment
+};
+ListLayout make_list_layout(int H, int W, int n_views, int edge_rows);
+
+// One frame as the kernels see it.  The prefix array holds the exclusive
+// prefix of the segment sizes in class-major order: the views of class 0 in
+// `vord` order, then class 1, ...; bands inner.
+struct FrameDesc {
+    const float* D;
+    uint8_t* M;
+    int H, W;
+    ListLayout ll;
+    uint32_t* lists;
+    int32_t* counts;
+    int32_t* prefix;
+    int gx, gy;                       // edge-pass blocks along x / y
+    int block_begin;                  // first flat edge-pass block (batched launch)
+    int h[OCCL_MAX_VIEWS];            // half scan length floor(L/2) per view
+    int vord[OCCL_MAX_VIEWS];         // views ordered by scan class (stable)
+    int cls_start[kNumClasses + 1];   // number of views of class < ci in vord
+};
+
+// Launch shape chosen by the autotuner.
+struct TuneConfig {
+    int edge_rows;           // 1..16
+    int scan_blocks_per_cu;  // persistent scanline blocks per compute unit
+};
+
+// Fills the fields of a FrameDesc that depend only on sizes and scan lengths
+// (layout, grid, class order); the workspace pointers are set by the caller.
+void describe_frame(FrameDesc* f, const float* D, uint8_t* M, int H, int W, int n_views,
+                    const int* Ls, int edge_rows);
 
 // ---- launchers (k_exact.hip) ------------------------------------------------
-hipError_t launch_edges_candidates(hipStream_t st, const float* D, int H, int W, uint8_t* M,
-                                   int n_views, const ViewTable& vt, float q_min,
-                                   const ListLayout& ll, uint32_t* lists, int32_t* counts,
-                                   int32_t* prefix);
+hipError_t launch_edges(hipStream_t st, const FrameDesc& f, int n_views, const ViewTable& vt,
+                        float q_min);
+hipError_t launch_scanlines(hipStream_t st, const FrameDesc& f, int n_views, const ViewTable& vt,
+                            const Thresholds& th, int cls, int n_blocks);
+hipError_t launch_edges_batched(hipStream_t st, const FrameDesc* table, int n_frames,
+                                int total_blocks, int n_views, const ViewTable& vt, float q_min,
+                                int edge_rows, int n_blocks);
+hipError_t launch_scanlines_batched(hipStream_t st, const FrameDesc* table, int n_frames,
+                                    int n_views, const ViewTable& vt, const Thresholds& th,
+                                    int cls, int n_blocks);
 
 // Smallest fp32 q >= 0 whose correctly rounded square root exceeds gamma
 // (-inf when gamma < 0: every magnitude passes).  Host only.
@@ -77,14 +123,7 @@ float edge_q_min(float gamma);
 // Thresholds of a validated occl_params (host only).
 Thresholds make_thresholds(const occl_params* p);
 
-// Processes the scanlines of every candidate of the views listed in `views`.
-// kclass 2 serves the views whose scanlines fit K = 1 or 2 samples per lane;
-// kclass 4, 8, 16 serve exactly that K.
-hipError_t launch_scanlines(hipStream_t st, const float* D, int H, int W, uint8_t* M,
-                            const ViewTable& vt, const Thresholds& th, const int* views,
-                            int n_list, int kclass, const ListLayout& ll, const uint32_t* lists,
-                            const int32_t* prefix, int n_blocks);
-
+// ---- helpers (k_util.hip) ---------------------------------------------------
 // min / max / non-finite count of D into dev[0..2] (orderable uint32 / count).
 hipError_t launch_scan_stats(hipStream_t st, const float* D, size_t n, uint32_t* dev);
 

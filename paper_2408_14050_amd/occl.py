@@ -57,6 +57,10 @@ class occl_frame(C.Structure):
     ]
 
 
+class occl_tune(C.Structure):
+    _fields_ = [("edge_rows", C.c_int32), ("scan_blocks_per_cu", C.c_int32), ("ms", C.c_float)]
+
+
 _lib = None
 
 # name -> (restype, argtypes); the same names as the C ABI
@@ -80,8 +84,16 @@ _SIGS = {
     "occl_direction": (C.c_int, [C.c_double, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
     "occl_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "occl_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "occl_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                C.POINTER(C.c_double), C.POINTER(C.c_float), C.POINTER(occl_params),
+                                C.c_void_p, C.c_int32, C.POINTER(occl_tune)]),
+    "occl_autotune_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(occl_frame), C.c_int32,
+                                        C.POINTER(C.c_double), C.POINTER(C.c_float),
+                                        C.POINTER(occl_params), C.c_int32, C.POINTER(occl_tune)]),
+    "occl_tune_save": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "occl_tune_load": (C.c_int, [C.c_void_p, C.c_char_p]),
 }
-STAGES = ("edges", "scanlines", "cnn", "fallback")
+STAGES = ("edges", "scanlines", "cnn", "fallback", "batched")
 
 
 def exported_symbols():
@@ -177,9 +189,8 @@ class Context:
         self._check(st, "occl_detect")
         return M
 
-    def occl_detect_batched(self, frames, angles, ratios, prm: occl_params):
-        """frames: list of (D, M, scan_len_per_view or None)."""
-        a, r = self._views(angles, ratios)
+    @staticmethod
+    def _frames(frames):
         arr = (occl_frame * max(1, len(frames)))()
         keep = []
         for i, (D, M, Ls) in enumerate(frames):
@@ -190,10 +201,43 @@ class Context:
                 l = np.ascontiguousarray(Ls, dtype=np.int32)
                 keep.append(l)
                 arr[i].scan_len_per_view = l.ctypes.data_as(C.POINTER(C.c_int32))
+        return arr, keep
+
+    def occl_detect_batched(self, frames, angles, ratios, prm: occl_params):
+        """frames: list of (D, M, scan_len_per_view or None)."""
+        a, r = self._views(angles, ratios)
+        arr, keep = self._frames(frames)
         st = lib().occl_detect_batched(self.h, len(frames), arr, int(a.shape[0]),
                                        a.ctypes.data_as(C.POINTER(C.c_double)),
                                        r.ctypes.data_as(C.POINTER(C.c_float)), C.byref(prm))
         self._check(st, "occl_detect_batched")
+
+    def occl_autotune(self, D, angles, ratios, prm: occl_params, M, reps: int = 10):
+        a, r = self._views(angles, ratios)
+        out = occl_tune()
+        st = lib().occl_autotune(self.h, _ptr(D), int(D.shape[0]), int(D.shape[1]), int(a.shape[0]),
+                                 a.ctypes.data_as(C.POINTER(C.c_double)),
+                                 r.ctypes.data_as(C.POINTER(C.c_float)), C.byref(prm), _ptr(M),
+                                 int(reps), C.byref(out))
+        self._check(st, "occl_autotune")
+        return {"edge_rows": out.edge_rows, "scan_blocks_per_cu": out.scan_blocks_per_cu, "ms": out.ms}
+
+    def occl_autotune_batched(self, frames, angles, ratios, prm: occl_params, reps: int = 5):
+        a, r = self._views(angles, ratios)
+        arr, keep = self._frames(frames)
+        out = occl_tune()
+        st = lib().occl_autotune_batched(self.h, len(frames), arr, int(a.shape[0]),
+                                         a.ctypes.data_as(C.POINTER(C.c_double)),
+                                         r.ctypes.data_as(C.POINTER(C.c_float)), C.byref(prm),
+                                         int(reps), C.byref(out))
+        self._check(st, "occl_autotune_batched")
+        return {"edge_rows": out.edge_rows, "scan_blocks_per_cu": out.scan_blocks_per_cu, "ms": out.ms}
+
+    def occl_tune_save(self, path: str):
+        self._check(lib().occl_tune_save(self.h, path.encode()), "occl_tune_save")
+
+    def occl_tune_load(self, path: str):
+        self._check(lib().occl_tune_load(self.h, path.encode()), "occl_tune_load")
 
     def occl_last_candidate_counts(self, n_views: int):
         out = np.zeros(n_views, np.int64)
