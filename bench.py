@@ -118,6 +118,7 @@ def cpu_baseline(sc, seconds: float):
 # ---------------------------------------------------------------------------
 PROFILE_CMD = ("rocprofv3 {mode} -d gpurun_out/{out} -o run -- python3 bench.py --steps 20 "
                "--warmup 2 --no-cpu-baseline --no-context --no-check")
+BATCH_WORKLOAD = "c3 64 mixed frames seed 3000"
 COPY_CMD = "rocprofv3 --pmc {ctr} -d gpurun_out/{out} -o run -- python3 bench.py --copy-probe 256"
 
 
@@ -185,16 +186,17 @@ def profiles_from(run_dir: str, workload: str) -> int:
     traffic = {"copy_probe": {"mib": 256, "fetch_kib": max(cf.values()) if cf else None,
                               "write_kib": max(cw.values()) if cw else None,
                               "read_factor": f_read, "write_factor": f_write}}
-    tag = workload.replace(" ", "_").replace("x8_views", "v8")
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     for k in sorted(k for k in set(trace) & set(fetch) & set(write) if k.startswith("k_")):
+        wl = BATCH_WORKLOAD if "batched" in k else workload
+        tag = wl.split(":")[0].replace(" ", "_").replace("x8_views", "v8")
         rd = fetch[k] * 1024 / (f_read or 1.0)
         wr = write[k] * 1024 / (f_write or 1.0)
-        traffic[k] = {"kernel_hash": kernel_hash(), "workload": workload, "fetch_kib": fetch[k],
+        traffic[k] = {"kernel_hash": kernel_hash(), "workload": wl, "fetch_kib": fetch[k],
                       "write_kib": write[k], "bytes_per_launch": round(rd + wr),
                       "read_bytes": round(rd), "write_bytes": round(wr)}
         lines = [
-            f"# {k} -- {workload}",
+            f"# {k} -- {wl}",
             "",
             "Commands (from the repository root on the GPU box):",
             "  " + PROFILE_CMD.format(mode="--kernel-trace --stats", out="prof"),

@@ -14,8 +14,9 @@
 //                    segment counters into a class-major prefix for the
 //                    scanline pass and clears them for the next frame.
 //   scanline pass    one wavefront per candidate scanline (Eqs. 4-6), the
-//                    (view, candidate) pairs handed out flat, one contiguous
-//                    chunk per wavefront, so long and short lists balance.
+//                    (view, candidate) pairs handed out flat in small groups,
+//                    round-robin, so long and short lists balance and all
+//                    wavefronts sweep the list (and D) together.
 //                    A scanline of n <= 64*K samples holds K samples per lane.
 //                    Ordering by (W, g): W split into maximal non-decreasing
 //                    runs; one run is already sorted; up to a few runs are
@@ -536,6 +537,8 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
 template <int KMAX>
 constexpr int waves_per_block() { return KMAX >= 16 ? 2 : 4; }
 
+constexpr int kGroup = 4;  // consecutive work items per wavefront visit
+
 // The scanline of candidate `pix` of view v of frame f.
 template <int KMAX>
 __device__ __forceinline__ void scan_item(const FrameDesc& f, int v, uint32_t pix,
@@ -564,7 +567,7 @@ __device__ __forceinline__ void segment_of(const FrameDesc& f, int cls, int lo, 
     *seg = *v * C + lo % C;
 }
 
-// One frame, the views of scan class cls: a flat, chunked walk over every
+// One frame, the views of scan class cls: a flat walk over every
 // (view, candidate) pair of the class.
 template <int KMAX>
 __global__ __launch_bounds__(64 * waves_per_block<KMAX>()) void k_scanlines(
@@ -585,25 +588,26 @@ __global__ __launch_bounds__(64 * waves_per_block<KMAX>()) void k_scanlines(
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const WaveLds L{lds[wave][0], lds[wave][1], okeys[wave], lds[wave][2], lds[wave][3], runs[wave]};
+    // Blocked round-robin: wavefront gw takes groups of kGroup consecutive
+    // items at gw*kGroup, gw*kGroup + nw*kGroup, ...  All wavefronts sweep the
+    // list together (a small live working set of D), and within a group the
+    // segment is found by stepping forward.
     const int nw = gridDim.x * WPB;
     const int gw = blockIdx.x * WPB + wave;
-    const int chunk = (total + nw - 1) / nw;
-    const int t_end = min(total, (gw + 1) * chunk);
-    int lo = 0;
-    if (gw * chunk < t_end) {  // segment of the first item: last with pre <= t
-        int hi = nseg - 1;
-        const int t0 = gw * chunk;
+    for (int g0 = gw * kGroup; g0 < total; g0 += nw * kGroup) {
+        const int g1 = min(total, g0 + kGroup);
+        int lo = 0, hi = nseg - 1;  // segment of the group's first item: last with pre <= g0
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (pre[mid] <= t0) lo = mid; else hi = mid - 1;
+            if (pre[mid] <= g0) lo = mid; else hi = mid - 1;
         }
-    }
-    for (int t = gw * chunk; t < t_end; ++t) {
-        while (lo + 1 < nseg && pre[lo + 1] <= t) ++lo;
-        int v, seg;
-        segment_of(f, cls, lo, &v, &seg);
-        const uint32_t pix = f.lists[(size_t)seg * f.ll.cap + (size_t)(t - pre[lo])];
-        scan_item<KMAX>(f, v, pix, vt, th, L, lane);
+        for (int t = g0; t < g1; ++t) {
+            while (lo + 1 < nseg && pre[lo + 1] <= t) ++lo;
+            int v, seg;
+            segment_of(f, cls, lo, &v, &seg);
+            const uint32_t pix = f.lists[(size_t)seg * f.ll.cap + (size_t)(t - pre[lo])];
+            scan_item<KMAX>(f, v, pix, vt, th, L, lane);
+        }
     }
 }
 
@@ -662,40 +666,45 @@ __global__ __launch_bounds__(64 * waves_per_block<KMAX>()) void k_scanlines_batc
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const WaveLds L{lds[wave][0], lds[wave][1], okeys[wave], lds[wave][2], lds[wave][3], runs[wave]};
+    // blocked round-robin over the frame-major list (see k_scanlines): all
+    // wavefronts work on neighbouring frames at any time
     const int nw = gridDim.x * WPB;
     const int gw = blockIdx.x * WPB + wave;
-    const int chunk = (total + nw - 1) / nw;
-    const int t_end = min(total, (gw + 1) * chunk);
-    int fi = -1, lo = 0, nseg = 0, seg0 = 0, pbase = 0;
-    for (int t = gw * chunk; t < t_end; ++t) {
-        if (fi < 0 || t >= fpre[fi + 1]) {
-            // frame of item t (last with fpre <= t), then its segment by binary search
-            int a = fi < 0 ? 0 : fi, b = n_frames - 1;
-            while (a < b) {
-                const int mid = (a + b + 1) >> 1;
-                if (fpre[mid] <= t) a = mid; else b = mid - 1;
+    int fi = 0;
+    for (int g0 = gw * kGroup; g0 < total; g0 += nw * kGroup) {
+        const int g1 = min(total, g0 + kGroup);
+        int fi_cur = -1, lo = 0, nseg = 0, seg0 = 0, pbase = 0;
+        for (int t = g0; t < g1; ++t) {
+            if (fi_cur < 0 || t >= fpre[fi_cur + 1]) {
+                // frame of item t (last with fpre <= t), then its segment by binary search
+                int a = fi, b = n_frames - 1;
+                while (a < b) {
+                    const int mid = (a + b + 1) >> 1;
+                    if (fpre[mid] <= t) a = mid; else b = mid - 1;
+                }
+                fi = fi_cur = a;
+                const FrameDesc& f = table[fi_cur];
+                const int C = f.ll.copies;
+                seg0 = f.cls_start[cls] * C;
+                nseg = (f.cls_start[cls + 1] - f.cls_start[cls]) * C;
+                pbase = f.prefix[seg0];
+                const int u = t - fpre[fi_cur];
+                int p = 0, q = nseg - 1;
+                while (p < q) {
+                    const int mid = (p + q + 1) >> 1;
+                    if (f.prefix[seg0 + mid] - pbase <= u) p = mid; else q = mid - 1;
+                }
+                lo = p;
             }
-            fi = a;
-            const FrameDesc& f = table[fi];
-            const int C = f.ll.copies;
-            seg0 = f.cls_start[cls] * C;
-            nseg = (f.cls_start[cls + 1] - f.cls_start[cls]) * C;
-            pbase = f.prefix[seg0];
-            const int u = t - fpre[fi];
-            int p = 0, q = nseg - 1;
-            while (p < q) {
-                const int mid = (p + q + 1) >> 1;
-                if (f.prefix[seg0 + mid] - pbase <= u) p = mid; else q = mid - 1;
-            }
-            lo = p;
+            const FrameDesc& f = table[fi_cur];
+            const int u = t - fpre[fi_cur];
+            while (lo + 1 < nseg && f.prefix[seg0 + lo + 1] - pbase <= u) ++lo;
+            int v, seg;
+            segment_of(f, cls, lo, &v, &seg);
+            const uint32_t pix =
+                f.lists[(size_t)seg * f.ll.cap + (size_t)(u - (f.prefix[seg0 + lo] - pbase))];
+            scan_item<KMAX>(f, v, pix, vt, th, L, lane);
         }
-        const FrameDesc& f = table[fi];
-        const int u = t - fpre[fi];
-        while (lo + 1 < nseg && f.prefix[seg0 + lo + 1] - pbase <= u) ++lo;
-        int v, seg;
-        segment_of(f, cls, lo, &v, &seg);
-        const uint32_t pix = f.lists[(size_t)seg * f.ll.cap + (size_t)(u - (f.prefix[seg0 + lo] - pbase))];
-        scan_item<KMAX>(f, v, pix, vt, th, L, lane);
     }
 }
 
