@@ -171,6 +171,85 @@ occl_status occl_edges(occl_ctx* ctx, const float* D, int32_t H, int32_t W, floa
 occl_status occl_confusion(occl_ctx* ctx, const uint8_t* pred, const uint8_t* ref, int64_t n,
                            uint64_t* out);
 
+/* ---- learned tile proposal + exact fallback -------------------------------
+ * Not part of the paper: a small network proposes, per 16 x 16 pixel tile
+ * and view, the probability that the tile holds occluded pixels (the tile's
+ * occluded fraction of the exact mask of Sec. 3 is its training target).
+ * Confident tiles are filled, the rest take the exact path of Sec. 3
+ * restricted to them.  Network: six 3x3 convolutions 8->32 (stride 2),
+ * 32->32 (2), 32->32 (2), 32->32 (2), 32->32 (1), 32->1 (1), ReLU after all
+ * but the last; bf16 weights and activations, fp32 accumulation and logits.
+ * Parameters are one flat fp32 vector, layer by layer, each layer's weights
+ * [Cout][3][3][Cin] then its biases [Cout]. */
+
+/* Number of parameters of the network (39617). */
+size_t occl_cnn_num_params(void);
+
+/* Random initial weights (He-uniform from `seed`, zero biases), zero Adam
+ * state, step 0. */
+occl_status occl_cnn_init(occl_ctx* ctx, uint64_t seed);
+
+/* Model state for checkpoint / resume: parameters, Adam moments m and v
+ * (host fp32 [n] each; m, v may be NULL on set = zero, on get = skipped) and
+ * the Adam step count.  n must equal occl_cnn_num_params(); set rejects
+ * non-finite values with OCCL_ERR_INVALID_ARG and leaves the state as it was. */
+occl_status occl_cnn_set_state(occl_ctx* ctx, const float* theta, const float* m, const float* v,
+                               int64_t step, size_t n);
+occl_status occl_cnn_get_state(occl_ctx* ctx, float* theta, float* m, float* v, int64_t* step,
+                               size_t n);
+
+/* Network input of every view: device bf16 X [n_views][H][W][8] with the
+ * channels D * r / L, E / 8, cos A, sin A, cos alpha, sin alpha, r / 2, 0
+ * (E and A = atan2(E_y, E_x) of Eq. (1); (cos alpha, sin alpha) the view's
+ * direction; scan_len host int32 [n_views] >= 1). */
+occl_status occl_cnn_pack(occl_ctx* ctx, const float* D, int32_t H, int32_t W, int32_t n_views,
+                          const double* angles_deg, const float* ratios, const int32_t* scan_len,
+                          uint16_t* X);
+
+/* Logits of N inputs X (device bf16 [N][H][W][8]) into device fp32
+ * logits [N][ceil(H/16)][ceil(W/16)].  Needs weights (OCCL_ERR_NO_MODEL). */
+occl_status occl_cnn_forward(occl_ctx* ctx, const uint16_t* X, int32_t N, int32_t H, int32_t W,
+                             float* logits);
+
+/* Copies the output of hidden layer `layer` (0..4) of the most recent
+ * forward pass (occl_cnn_forward, _backward, _train_step or a USE_CNN
+ * detection) into dst: device bf16 [N][H_l][W_l][32] with n =
+ * N * H_l * W_l * 32 elements (H_l = H halved, rounding up, once per
+ * stride-2 layer up to `layer`).  For inspection and tests. */
+occl_status occl_cnn_activation(occl_ctx* ctx, int32_t layer, uint16_t* dst, size_t n);
+
+/* Mean soft binary cross-entropy of the logits against targets T (device fp32,
+ * same shape as the logits, values in [0, 1]) and its gradient.  `loss`
+ * (host, may be NULL) receives the loss; `grad` (host fp32
+ * [occl_cnn_num_params()], may be NULL) the gradient.  Synchronises when
+ * either is requested. */
+occl_status occl_cnn_backward(occl_ctx* ctx, const uint16_t* X, int32_t N, int32_t H, int32_t W,
+                              const float* T, double* loss, float* grad);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with
+ * learning rate lr > 0 on the gradient of occl_cnn_backward's loss. */
+occl_status occl_cnn_train_step(occl_ctx* ctx, const uint16_t* X, int32_t N, int32_t H, int32_t W,
+                                const float* T, float lr, double* loss);
+
+/* Training targets: the occluded fraction of every 16 x 16 tile (tiles
+ * aligned to (0, 0); edge tiles partial) of n masks M (device uint8
+ * [n][H][W]) into device fp32 T [n][ceil(H/16)][ceil(W/16)]. */
+occl_status occl_cnn_tile_targets(occl_ctx* ctx, const uint8_t* M, int32_t n, int32_t H, int32_t W,
+                                  float* T);
+
+/* Exact fallback routed by tile logits (device fp32 [n_views][ceil(H/16)][ceil(W/16)],
+ * from occl_cnn_forward or any other source).  A tile with logit
+ * z < log(lo / (1 - lo)) (lo = params->cnn_lo, computed in double, rounded to
+ * fp32) is written with 0s, one with z > log(hi / (1 - hi)) with 1s, and
+ * every other tile with exactly the mask occl_detect writes there.
+ * tile_state (device uint8, same shape as the logits, may be NULL) receives
+ * 0 / 1 for the filled tiles and 2 for the tiles that took the exact path.
+ * The other arguments are those of occl_detect. */
+occl_status occl_detect_routed(occl_ctx* ctx, const float* D, int32_t H, int32_t W, int32_t n_views,
+                               const double* angles_deg, const float* ratios,
+                               const occl_params* params, const float* logits, uint8_t* M,
+                               uint8_t* tile_state);
+
 /* Waits for the context's stream; reports a pending device error. */
 occl_status occl_sync(occl_ctx* ctx);
 

@@ -152,9 +152,10 @@ def adam(theta, grad, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def pack(D, angle_deg, ratio, L):
+def pack(D, c, s, ratio, L):
     """Input channels of one view: D*r/L, E/8, cos A, sin A, cos alpha,
-    sin alpha, r/2, 0 (A = atan2(E_y, E_x); E, E_x, E_y of Eq. (1)) -> bf16."""
+    sin alpha, r/2, 0 (A = atan2(E_y, E_x); E, E_x, E_y of Eq. (1);
+    (c, s) = (cos alpha, sin alpha), the view's direction vector) -> bf16."""
     D = np.asarray(D, np.float64)
     H, W = D.shape
     ex = np.zeros_like(D)
@@ -162,15 +163,18 @@ def pack(D, angle_deg, ratio, L):
     ex[:, :-1] = D[:, 1:] - D[:, :-1]
     ey[:-1, :] = D[1:, :] - D[:-1, :]
     E = np.sqrt(ex * ex + ey * ey)
-    A = np.arctan2(ey, ex)
-    a = np.radians(angle_deg)
+    # cos A and sin A of A = atan2(E_y, E_x), written as E_x / E and E_y / E
+    # (A = 0 where E = 0, as atan2(0, 0) = 0)
+    safe = np.where(E > 0, E, 1.0)
+    cosA = np.where(E > 0, ex / safe, 1.0)
+    sinA = np.where(E > 0, ey / safe, 0.0)
     x = np.zeros((H, W, IN_CH))
     x[..., 0] = D * (ratio / L)
     x[..., 1] = E / 8.0
-    x[..., 2] = np.cos(A)
-    x[..., 3] = np.sin(A)
-    x[..., 4] = np.cos(a)
-    x[..., 5] = np.sin(a)
+    x[..., 2] = cosA
+    x[..., 3] = sinA
+    x[..., 4] = c
+    x[..., 5] = s
     x[..., 6] = ratio / 2.0
     return bf16(x)
 

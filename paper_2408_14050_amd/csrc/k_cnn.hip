@@ -1,0 +1,544 @@
+// k_cnn.hip -- gfx950 kernels of the learned tile proposal: a 6-layer 3x3
+// convolutional network (8->32 s2, 32->32 s2, 32->32 s2, 32->32 s2,
+// 32->32 s1, 32->1 s1; ReLU after all but the last) in BF16 with FP32
+// accumulation, trained and run on MFMA.
+//
+// Layouts: activations NHWC bf16 [N][H][W][C]; weights [Cout][3][3][Cin]
+// (bf16 copy of fp32 master weights), biases fp32; logits fp32 [N][Ht][Wt].
+// Output size of a stride-s layer: ceil(H / s).
+//
+// The 32-output-channel layers are implicit GEMMs on
+// v_mfma_f32_32x32x8_bf16: one wavefront computes 32 output pixels x 32
+// channels; every K step of 8 is one tap (ky, kx) and 8 input channels,
+// i.e. one 16-byte row of the NHWC input (so the A operand of a lane is a
+// single 8-byte load).  Operand layout of the instruction (checked on the
+// device): lane l supplies A[l % 32][4*(l/32) + i] and B[4*(l/32) + i][l % 32],
+// i = 0..3, and accumulator register j of lane l holds
+// D[8*(j/4) + 4*(l/32) + (j%4)][l % 32].
+//   forward  M = output pixels, N = output channels, K = 9 * Cin
+//   dgrad    M = input pixels,  N = input channels,  K = 9 * Cout (weights
+//            pre-transposed to [tap][Cin][Cout]; invalid taps of a strided
+//            layer contribute zeros)
+//   wgrad    M = output channels, N = (tap, Cin) columns, K = pixels; split
+//            over pixel chunks into FP32 partials that a second kernel sums
+//            in a fixed order (deterministic)
+// The 1-channel last layer and the loss use plain VALU kernels.
+#include "occl_cnn.h"
+
+namespace occl {
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return 0x7fc0;  // NaN
+    u += 0x7fffu + ((u >> 16) & 1u);                                            // nearest, ties to even
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ bf16x4 load4(const uint16_t* p) {
+    return *reinterpret_cast<const bf16x4*>(p);
+}
+
+// ---------------------------------------------------------------------------
+// input pack: per view, D * r / L, E / 8, cos A, sin A, cos alpha, sin alpha,
+// r / 2, 0 (A = atan2(E_y, E_x) of the forward-difference edge maps)
+// ---------------------------------------------------------------------------
+struct PackViews {
+    float c[OCCL_MAX_VIEWS], s[OCCL_MAX_VIEWS], r[OCCL_MAX_VIEWS], inv_L[OCCL_MAX_VIEWS];
+};
+
+__global__ __launch_bounds__(256) void k_pack(const float* __restrict__ D, int H, int W, int n_views,
+                                              PackViews pv, uint16_t* __restrict__ X) {
+    const size_t HW = (size_t)H * W;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < HW;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int y = (int)(i / W), x = (int)(i % W);
+        const float d = D[i];
+        const float ex = (x + 1 < W) ? D[i + 1] - d : 0.0f;
+        const float ey = (y + 1 < H) ? D[i + W] - d : 0.0f;
+        const float E = sqrtf(ex * ex + ey * ey);
+        const float ca = E > 0.0f ? ex / E : 1.0f;
+        const float sa = E > 0.0f ? ey / E : 0.0f;
+        for (int v = 0; v < n_views; ++v) {
+            uint16_t o[8];
+            o[0] = f2bf(d * pv.r[v] * pv.inv_L[v]);
+            o[1] = f2bf(E * 0.125f);
+            o[2] = f2bf(ca);
+            o[3] = f2bf(sa);
+            o[4] = f2bf(pv.c[v]);
+            o[5] = f2bf(pv.s[v]);
+            o[6] = f2bf(pv.r[v] * 0.5f);
+            o[7] = 0;
+            uint4 q;
+            q.x = o[0] | ((uint32_t)o[1] << 16);
+            q.y = o[2] | ((uint32_t)o[3] << 16);
+            q.z = o[4] | ((uint32_t)o[5] << 16);
+            q.w = o[6] | ((uint32_t)o[7] << 16);
+            *reinterpret_cast<uint4*>(X + ((size_t)v * HW + i) * 8) = q;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// forward, 32 output channels, bias + ReLU (MFMA implicit GEMM)
+// ---------------------------------------------------------------------------
+template <int CIN, int S>
+__global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ X,
+                                                  const uint16_t* __restrict__ Wt,
+                                                  const float* __restrict__ bias,
+                                                  uint16_t* __restrict__ Y, int N, int H, int W,
+                                                  int Ho, int Wo) {
+    const int lane = threadIdx.x & 63;
+    const int q = lane >> 5, i32 = lane & 31;
+    const long total = (long)N * Ho * Wo;
+    const long m0 = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 32;
+    if (m0 >= total) return;
+    const long p = m0 + i32;  // the A row this lane loads
+    const bool pv = p < total;
+    const int n = pv ? (int)(p / ((long)Ho * Wo)) : 0;
+    const int rem = pv ? (int)(p % ((long)Ho * Wo)) : 0;
+    const int oy = rem / Wo, ox = rem % Wo;
+    f32x16 acc = {};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int iy = oy * S + t / 3 - 1, ix = ox * S + t % 3 - 1;
+        const bool in = pv && iy >= 0 && iy < H && ix >= 0 && ix < W;
+        const uint16_t* xrow = X + (((size_t)n * H + (in ? iy : 0)) * W + (in ? ix : 0)) * CIN;
+        const uint16_t* wrow = Wt + ((size_t)i32 * 9 + t) * CIN;
+#pragma unroll
+        for (int cc = 0; cc < CIN / 8; ++cc) {
+            const bf16x4 a = in ? load4(xrow + 8 * cc + 4 * q) : bf16x4{0, 0, 0, 0};
+            const bf16x4 b = load4(wrow + 8 * cc + 4 * q);
+            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+        }
+    }
+    const float bv = bias[i32];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const long pr = m0 + 8 * (j / 4) + 4 * q + (j % 4);
+        if (pr < total) {
+            const float v = acc[j] + bv;
+            Y[pr * 32 + i32] = f2bf(v > 0.0f ? v : 0.0f);
+        }
+    }
+}
+
+// last layer: 32 -> 1, stride 1, no activation, fp32 logits
+__global__ __launch_bounds__(256) void k_conv_last(const uint16_t* __restrict__ X,
+                                                   const uint16_t* __restrict__ Wt,
+                                                   const float* __restrict__ bias,
+                                                   float* __restrict__ Z, int N, int H, int W) {
+    const long total = (long)N * H * W;
+    for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < total;
+         p += (long)gridDim.x * blockDim.x) {
+        const int n = (int)(p / ((long)H * W));
+        const int rem = (int)(p % ((long)H * W));
+        const int oy = rem / W, ox = rem % W;
+        float acc = bias[0];
+        for (int t = 0; t < 9; ++t) {
+            const int iy = oy + t / 3 - 1, ix = ox + t % 3 - 1;
+            if (iy < 0 || iy >= H || ix < 0 || ix >= W) continue;
+            const uint16_t* xr = X + (((size_t)n * H + iy) * W + ix) * 32;
+            const uint16_t* wr = Wt + t * 32;
+            for (int ci = 0; ci < 32; ++ci) acc += bf2f(xr[ci]) * bf2f(wr[ci]);
+        }
+        Z[p] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// loss: soft binary cross-entropy on the logits, mean over all tiles
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_bce(const float* __restrict__ Z, const float* __restrict__ T,
+                                             float* __restrict__ dZ, double* __restrict__ partial,
+                                             long n) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    const float inv = 1.0f / (float)n;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x) {
+        const float z = Z[i], t = T[i];
+        const float sg = 1.0f / (1.0f + expf(-z));
+        dZ[i] = (sg - t) * inv;
+        acc += (double)(fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z))) - t * z);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// backward of the last layer (32 -> 1, stride 1)
+// ---------------------------------------------------------------------------
+// dX[n][y][x][ci] = sum_t dZ[n][y - ky + 1][x - kx + 1] * w[t][ci]  -> bf16
+__global__ __launch_bounds__(256) void k_dgrad_last(const float* __restrict__ dZ,
+                                                    const uint16_t* __restrict__ Wt,
+                                                    uint16_t* __restrict__ dX, int N, int H, int W) {
+    const long total = (long)N * H * W * 32;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (long)gridDim.x * blockDim.x) {
+        const int ci = (int)(i & 31);
+        const long p = i >> 5;
+        const int n = (int)(p / ((long)H * W));
+        const int rem = (int)(p % ((long)H * W));
+        const int y = rem / W, x = rem % W;
+        float acc = 0.0f;
+        for (int t = 0; t < 9; ++t) {
+            const int oy = y - t / 3 + 1, ox = x - t % 3 + 1;
+            if (oy < 0 || oy >= H || ox < 0 || ox >= W) continue;
+            acc += dZ[((size_t)n * H + oy) * W + ox] * bf2f(Wt[t * 32 + ci]);
+        }
+        dX[i] = f2bf(acc);
+    }
+}
+
+// partial sums over pixel chunks of dW[t][ci] = sum_p dZ[p] X[in(p, t)][ci]
+// and db = sum_p dZ[p]: block b handles chunk b, thread k column k (288 + 1)
+__global__ __launch_bounds__(320) void k_wgrad_last(const float* __restrict__ dZ,
+                                                    const uint16_t* __restrict__ X,
+                                                    float* __restrict__ partial, int N, int H, int W,
+                                                    int chunk) {
+    const int k = threadIdx.x;
+    if (k > 288) return;
+    const long total = (long)N * H * W;
+    const long p0 = (long)blockIdx.x * chunk;
+    const long p1 = p0 + chunk < total ? p0 + chunk : total;
+    float acc = 0.0f;
+    const int t = k / 32, ci = k % 32;
+    for (long p = p0; p < p1; ++p) {
+        const float g = dZ[p];
+        if (k == 288) {
+            acc += g;
+            continue;
+        }
+        const int n = (int)(p / ((long)H * W));
+        const int rem = (int)(p % ((long)H * W));
+        const int iy = rem / W + t / 3 - 1, ix = rem % W + t % 3 - 1;
+        if (iy < 0 || iy >= H || ix < 0 || ix >= W) continue;
+        acc += g * bf2f(X[(((size_t)n * H + iy) * W + ix) * 32 + ci]);
+    }
+    partial[(size_t)blockIdx.x * 289 + k] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// backward of a 32-output-channel layer with ReLU: g = dY * [Y > 0]
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bf16x4 relu_grad4(const uint16_t* dy, const uint16_t* y) {
+    const bf16x4 g = load4(dy), a = load4(y);
+    bf16x4 o;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o[i] = (bf2f((uint16_t)a[i]) > 0.0f) ? g[i] : (short)0;
+    return o;
+}
+
+// dX (bf16 [N][H][W][32]) of a layer with CIN = 32 input channels; WT is the
+// weight transposed to [tap][ci][co].
+template <int S>
+__global__ __launch_bounds__(256) void k_conv_dgrad(const uint16_t* __restrict__ dY,
+                                                    const uint16_t* __restrict__ Y,
+                                                    const uint16_t* __restrict__ WT,
+                                                    uint16_t* __restrict__ dX, int N, int H, int W,
+                                                    int Ho, int Wo) {
+    const int lane = threadIdx.x & 63;
+    const int q = lane >> 5, i32 = lane & 31;
+    const long total = (long)N * H * W;
+    const long m0 = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 32;
+    if (m0 >= total) return;
+    const long p = m0 + i32;
+    const bool pv = p < total;
+    const int n = pv ? (int)(p / ((long)H * W)) : 0;
+    const int rem = pv ? (int)(p % ((long)H * W)) : 0;
+    const int iy = rem / W, ix = rem % W;
+    f32x16 acc = {};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int ny = iy + 1 - t / 3, nx = ix + 1 - t % 3;  // = oy * S, ox * S
+        const int oy = ny / S, ox = nx / S;
+        const bool ok = pv && ny >= 0 && nx >= 0 && (ny % S) == 0 && (nx % S) == 0 && oy < Ho && ox < Wo;
+        const size_t o = (((size_t)n * Ho + (ok ? oy : 0)) * Wo + (ok ? ox : 0)) * 32;
+        const uint16_t* wrow = WT + ((size_t)t * 32 + i32) * 32;
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+            const bf16x4 a = ok ? relu_grad4(dY + o + 8 * cc + 4 * q, Y + o + 8 * cc + 4 * q)
+                                : bf16x4{0, 0, 0, 0};
+            const bf16x4 b = load4(wrow + 8 * cc + 4 * q);
+            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const long pr = m0 + 8 * (j / 4) + 4 * q + (j % 4);
+        if (pr < total) dX[pr * 32 + i32] = f2bf(acc[j]);
+    }
+}
+
+// wgrad partials of a 32-output-channel layer: block (chunk, tile) computes
+// the 32 x 32 tile of columns [32*tile, 32*tile + 32) of dW[co][t*CIN + ci]
+// over the chunk's pixels; partial layout [chunk][32][9*CIN].
+template <int CIN, int S>
+__global__ __launch_bounds__(64) void k_conv_wgrad(const uint16_t* __restrict__ dY,
+                                                   const uint16_t* __restrict__ Y,
+                                                   const uint16_t* __restrict__ X,
+                                                   float* __restrict__ partial, int N, int H, int W,
+                                                   int Ho, int Wo, int chunk) {
+    constexpr int NCOL = 9 * CIN;
+    const int lane = threadIdx.x;
+    const int q = lane >> 5, i32 = lane & 31;
+    const long total = (long)N * Ho * Wo;
+    const long p0 = (long)blockIdx.x * chunk;
+    const int col = blockIdx.y * 32 + i32;  // B column of this lane
+    const bool cvalid = col < NCOL;
+    const int t = cvalid ? col / CIN : 0, ci = cvalid ? col % CIN : 0;
+    f32x16 acc = {};
+    for (int k0 = 0; k0 < chunk; k0 += 8) {
+        bf16x4 a, b;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const long p = p0 + k0 + 4 * q + i;
+            short av = 0, bv = 0;
+            if (p < total && p < p0 + chunk) {
+                const size_t o = (size_t)p * 32 + i32;  // A[co = i32][k = p]
+                av = (bf2f(Y[o]) > 0.0f) ? (short)dY[o] : (short)0;
+                if (cvalid) {
+                    const int n = (int)(p / ((long)Ho * Wo));
+                    const int rem = (int)(p % ((long)Ho * Wo));
+                    const int iy = (rem / Wo) * S + t / 3 - 1, ix = (rem % Wo) * S + t % 3 - 1;
+                    if (iy >= 0 && iy < H && ix >= 0 && ix < W)
+                        bv = (short)X[(((size_t)n * H + iy) * W + ix) * CIN + ci];
+                }
+            }
+            a[i] = av;
+            b[i] = bv;
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    float* out = partial + (size_t)blockIdx.x * 32 * NCOL;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int co = 8 * (j / 4) + 4 * q + (j % 4);
+        if (cvalid) out[(size_t)co * NCOL + col] = acc[j];
+    }
+}
+
+// bias gradient partials of a 32-channel layer with ReLU: [chunk][32]
+__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ dY,
+                                                   const uint16_t* __restrict__ Y,
+                                                   float* __restrict__ partial, long total,
+                                                   int chunk) {
+    __shared__ float red[8][32];
+    const int co = threadIdx.x & 31, part = threadIdx.x >> 5;
+    const long p0 = (long)blockIdx.x * chunk;
+    const long p1 = p0 + chunk < total ? p0 + chunk : total;
+    float acc = 0.0f;
+    for (long p = p0 + part; p < p1; p += 8) {
+        const size_t o = (size_t)p * 32 + co;
+        if (bf2f(Y[o]) > 0.0f) acc += bf2f(dY[o]);
+    }
+    red[part][co] = acc;
+    __syncthreads();
+    if (part == 0) {
+        float s = 0.0f;
+        for (int k = 0; k < 8; ++k) s += red[k][co];
+        partial[(size_t)blockIdx.x * 32 + co] = s;
+    }
+}
+
+// out[k] = sum over chunks c (in order) of partial[c][k]
+__global__ __launch_bounds__(256) void k_reduce_chunks(const float* __restrict__ partial,
+                                                       float* __restrict__ out, int n_chunks,
+                                                       int n_out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_out) return;
+    float s = 0.0f;
+    for (int c = 0; c < n_chunks; ++c) s += partial[(size_t)c * n_out + k];
+    out[k] = s;
+}
+
+// WT[tap][ci][co] = W[co][tap][ci] (bf16) for the dgrad of a 32x32 layer
+__global__ __launch_bounds__(256) void k_transpose_w(const uint16_t* __restrict__ Wt,
+                                                     uint16_t* __restrict__ WT) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;  // over co, t, ci
+    if (i >= 32 * 9 * 32) return;
+    const int co = i / 288, t = (i / 32) % 9, ci = i % 32;
+    WT[((size_t)t * 32 + ci) * 32 + co] = Wt[i];
+}
+
+// Adam with bias correction on fp32 master weights; refreshes the bf16 copy
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ theta, const float* __restrict__ grad,
+                                              float* __restrict__ m, float* __restrict__ v,
+                                              uint16_t* __restrict__ wbf, int n, float lr, float b1,
+                                              float b2, float omb1, float omb2, float eps, float bc1,
+                                              float bc2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float g = grad[i];
+    const float mi = b1 * m[i] + omb1 * g;  // omb = 1 - b, rounded once from the exact value
+    const float vi = b2 * v[i] + omb2 * g * g;
+    m[i] = mi;
+    v[i] = vi;
+    const float th = theta[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    theta[i] = th;
+    wbf[i] = f2bf(th);
+}
+
+__global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ a, uint16_t* __restrict__ b,
+                                                 int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = f2bf(a[i]);
+}
+
+// occluded fraction of every 16x16 tile (edge tiles partial): M uint8 [n][H][W]
+__global__ __launch_bounds__(256) void k_tile_targets(const uint8_t* __restrict__ M, int n, int H,
+                                                      int W, float* __restrict__ T) {
+    const int Ht = (H + 15) / 16, Wt = (W + 15) / 16;
+    const long total = (long)n * Ht * Wt;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (long)gridDim.x * blockDim.x) {
+        const int k = (int)(i / ((long)Ht * Wt));
+        const int rem = (int)(i % ((long)Ht * Wt));
+        const int ty = rem / Wt, tx = rem % Wt;
+        const int y1 = min(H, ty * 16 + 16), x1 = min(W, tx * 16 + 16);
+        int cnt = 0;
+        for (int y = ty * 16; y < y1; ++y)
+            for (int x = tx * 16; x < x1; ++x) cnt += M[((size_t)k * H + y) * W + x] != 0;
+        T[i] = (float)cnt / (float)((y1 - ty * 16) * (x1 - tx * 16));
+    }
+}
+
+inline int blocks_for(long n, int per, int cap) {
+    long g = (n + per - 1) / per;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t cnn_pack(hipStream_t st, const float* D, int H, int W, int n_views, const ViewTable& vt,
+                    const int* Ls, uint16_t* X) {
+    PackViews pv{};
+    for (int v = 0; v < n_views; ++v) {
+        pv.c[v] = vt.c[v];
+        pv.s[v] = vt.s[v];
+        pv.r[v] = vt.r[v];
+        pv.inv_L[v] = 1.0f / (float)Ls[v];
+    }
+    hipLaunchKernelGGL(k_pack, dim3(blocks_for((long)H * W, 256, 16384)), dim3(256), 0, st, D, H, W,
+                       n_views, pv, X);
+    return hipGetLastError();
+}
+
+hipError_t cnn_conv_fwd(hipStream_t st, int cin, int stride, const uint16_t* X, const uint16_t* Wt,
+                        const float* b, uint16_t* Y, int N, int H, int W, int Ho, int Wo) {
+    const long waves = ((long)N * Ho * Wo + 31) / 32;
+    const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
+    if (cin == 8 && stride == 2)
+        hipLaunchKernelGGL((k_conv_fwd<8, 2>), grid, block, 0, st, X, Wt, b, Y, N, H, W, Ho, Wo);
+    else if (cin == 32 && stride == 2)
+        hipLaunchKernelGGL((k_conv_fwd<32, 2>), grid, block, 0, st, X, Wt, b, Y, N, H, W, Ho, Wo);
+    else if (cin == 32 && stride == 1)
+        hipLaunchKernelGGL((k_conv_fwd<32, 1>), grid, block, 0, st, X, Wt, b, Y, N, H, W, Ho, Wo);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t cnn_conv_last(hipStream_t st, const uint16_t* X, const uint16_t* Wt, const float* b,
+                         float* Z, int N, int H, int W) {
+    hipLaunchKernelGGL(k_conv_last, dim3(blocks_for((long)N * H * W, 256, 65535)), dim3(256), 0, st,
+                       X, Wt, b, Z, N, H, W);
+    return hipGetLastError();
+}
+
+hipError_t cnn_bce(hipStream_t st, const float* Z, const float* T, float* dZ, double* partial, long n,
+                   int n_blocks) {
+    hipLaunchKernelGGL(k_bce, dim3(n_blocks), dim3(256), 0, st, Z, T, dZ, partial, n);
+    return hipGetLastError();
+}
+
+hipError_t cnn_last_backward(hipStream_t st, const float* dZ, const uint16_t* X, const uint16_t* Wt,
+                             uint16_t* dX, float* partial, float* gw_out, int N, int H, int W) {
+    const long total = (long)N * H * W;
+    const int chunk = 256;
+    const int n_chunks = (int)((total + chunk - 1) / chunk);
+    hipLaunchKernelGGL(k_wgrad_last, dim3(n_chunks), dim3(320), 0, st, dZ, X, partial, N, H, W, chunk);
+    hipLaunchKernelGGL(k_reduce_chunks, dim3((289 + 255) / 256), dim3(256), 0, st, partial, gw_out,
+                       n_chunks, 289);
+    hipLaunchKernelGGL(k_dgrad_last, dim3(blocks_for(total * 32, 256, 65535)), dim3(256), 0, st, dZ, Wt,
+                       dX, N, H, W);
+    return hipGetLastError();
+}
+
+size_t cnn_wgrad_partial_floats(long pixels, int cin) {
+    const int chunk = 512;
+    const long n_chunks = (pixels + chunk - 1) / chunk;
+    return (size_t)n_chunks * 32 * 9 * cin + (size_t)n_chunks * 32;
+}
+
+// gw_out: dW [32][9*cin] then db [32]
+hipError_t cnn_layer_backward(hipStream_t st, int cin, int stride, const uint16_t* dY,
+                              const uint16_t* Y, const uint16_t* X, const uint16_t* Wt,
+                              uint16_t* WT, uint16_t* dX, float* partial, float* gw_out, int N, int H,
+                              int W, int Ho, int Wo) {
+    const long total = (long)N * Ho * Wo;
+    const int chunk = 512;
+    const int n_chunks = (int)((total + chunk - 1) / chunk);
+    const int ncol = 9 * cin;
+    const dim3 wg(n_chunks, (ncol + 31) / 32);
+    if (cin == 8 && stride == 2)
+        hipLaunchKernelGGL((k_conv_wgrad<8, 2>), wg, dim3(64), 0, st, dY, Y, X, partial, N, H, W, Ho, Wo, chunk);
+    else if (cin == 32 && stride == 2)
+        hipLaunchKernelGGL((k_conv_wgrad<32, 2>), wg, dim3(64), 0, st, dY, Y, X, partial, N, H, W, Ho, Wo, chunk);
+    else if (cin == 32 && stride == 1)
+        hipLaunchKernelGGL((k_conv_wgrad<32, 1>), wg, dim3(64), 0, st, dY, Y, X, partial, N, H, W, Ho, Wo, chunk);
+    else
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_reduce_chunks, dim3((32 * ncol + 255) / 256), dim3(256), 0, st, partial, gw_out,
+                       n_chunks, 32 * ncol);
+    float* bpart = partial + (size_t)n_chunks * 32 * ncol;
+    hipLaunchKernelGGL(k_bias_grad, dim3(n_chunks), dim3(256), 0, st, dY, Y, bpart, total, chunk);
+    hipLaunchKernelGGL(k_reduce_chunks, dim3(1), dim3(256), 0, st, bpart, gw_out + 32 * ncol, n_chunks, 32);
+    if (dX) {  // input gradient (not needed for the first layer)
+        if (cin != 32) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_transpose_w, dim3((32 * 9 * 32 + 255) / 256), dim3(256), 0, st, Wt, WT);
+        const long waves = ((long)N * H * W + 31) / 32;
+        const dim3 grid((unsigned)((waves + 3) / 4));
+        if (stride == 2)
+            hipLaunchKernelGGL(k_conv_dgrad<2>, grid, dim3(256), 0, st, dY, Y, WT, dX, N, H, W, Ho, Wo);
+        else
+            hipLaunchKernelGGL(k_conv_dgrad<1>, grid, dim3(256), 0, st, dY, Y, WT, dX, N, H, W, Ho, Wo);
+    }
+    return hipGetLastError();
+}
+
+hipError_t cnn_adam(hipStream_t st, float* theta, const float* grad, float* m, float* v, uint16_t* wbf,
+                    int n, float lr, double b1, double b2, double eps, double bc1, double bc2) {
+    hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, st, theta, grad, m, v, wbf, n, lr,
+                       (float)b1, (float)b2, (float)(1.0 - b1), (float)(1.0 - b2), (float)eps,
+                       (float)bc1, (float)bc2);
+    return hipGetLastError();
+}
+
+hipError_t cnn_to_bf16(hipStream_t st, const float* a, uint16_t* b, int n) {
+    hipLaunchKernelGGL(k_to_bf16, dim3((n + 255) / 256), dim3(256), 0, st, a, b, n);
+    return hipGetLastError();
+}
+
+hipError_t cnn_tile_targets(hipStream_t st, const uint8_t* M, int n, int H, int W, float* T) {
+    const long tiles = (long)n * ((H + 15) / 16) * ((W + 15) / 16);
+    hipLaunchKernelGGL(k_tile_targets, dim3(blocks_for(tiles, 256, 65535)), dim3(256), 0, st, M, n, H, W, T);
+    return hipGetLastError();
+}
+
+}  // namespace occl

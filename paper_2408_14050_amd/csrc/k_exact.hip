@@ -204,12 +204,17 @@ __device__ void edge_block(const FrameDesc& f, int bx, int by, int n_views, cons
             const int band = by / f.ll.block_rows_per_copy;
             for (int v = 0; v < n_views; ++v) {
                 const float c = vt.c[v], s = vt.s[v];
+                // routed frames keep only candidates that can reach an exact tile
+                // (x0 .. x0 + 3 share one tile)
+                const bool near =
+                    !f.tnear || (live && f.tnear[((size_t)v * ((H + kTile - 1) / kTile) + y / kTile) *
+                                                     f.tiles_x + x0 / kTile]);
                 uint64_t b[4];
                 int m4 = 0;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const float dot = __fadd_rn(__fmul_rn(ex[j], c), __fmul_rn(ey[j], s));
-                    const bool cand = strong[j] && (dot > 0.0f);
+                    const bool cand = strong[j] && (dot > 0.0f) && near;
                     m4 |= cand ? (1 << j) : 0;
                     b[j] = __ballot(cand);
                 }
@@ -230,14 +235,19 @@ __device__ void edge_block(const FrameDesc& f, int bx, int by, int n_views, cons
         }
         if (live) {
             const size_t HW = (size_t)H * W;
+            const int tiles_y = (H + kTile - 1) / kTile;
             for (int v = 0; v < n_views; ++v) {
                 uint8_t* mrow = f.M + v * HW + (size_t)y * W;
+                // a routed frame starts filled tiles at their fill value
+                const uint8_t fill =
+                    f.tstate ? (f.tstate[((size_t)v * tiles_y + y / kTile) * f.tiles_x + x0 / kTile] == 1)
+                             : 0;
                 if (vec) {
-                    *reinterpret_cast<uint32_t*>(mrow + x0) = 0u;
+                    *reinterpret_cast<uint32_t*>(mrow + x0) = 0x01010101u * fill;
                 } else {
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
-                        if (x0 + j < W) mrow[x0 + j] = 0;
+                        if (x0 + j < W) mrow[x0 + j] = fill;
                 }
             }
         }
@@ -364,18 +374,25 @@ __device__ __forceinline__ bool key_less(float wa, int ea, float wb, int eb) {
     return wa < wb || (wa == wb && ea < eb);
 }
 
+// Tile states of one view of a routed frame (t == NULL: plain exact path).
+struct TileView {
+    const uint8_t* t;
+    int tiles_x;
+};
+
 template <int K>
 __device__ __forceinline__ void mark_hit(uint8_t* __restrict__ Mv, int W, int cx, int cy, float c,
-                                         float s, int g) {
+                                         float s, int g, TileView tv) {
     const float gf = (float)g;
     const int ix = (int)rintf(__fadd_rn((float)cx, __fmul_rn(c, gf)));
     const int iy = (int)rintf(__fadd_rn((float)cy, __fmul_rn(s, gf)));
+    if (tv.t && tv.t[(iy / kTile) * tv.tiles_x + ix / kTile] != 2) return;  // filled tile
     Mv[(size_t)iy * W + ix] = 1;
 }
 
 template <int K>
 __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int W,
-                                         uint8_t* __restrict__ Mv, int cx, int cy, float c,
+                                         uint8_t* __restrict__ Mv, TileView tv, int cx, int cy, float c,
                                          float s, float r, int h, const Thresholds& th,
                                          const WaveLds& L, int lane) {
     constexpr int N = 64 * K;
@@ -529,7 +546,7 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
             hit |= (p + d < nvalid) & (fabsf(__fsub_rn(Wp, wr)) < th.zeta) &
                    (__fsub_rn(vr, Vp) > th.beta);
         }
-        if (valid & hit) mark_hit<K>(Mv, W, cx, cy, c, s, e - h);
+        if (valid & hit) mark_hit<K>(Mv, W, cx, cy, c, s, e - h, tv);
     }
     wave_lds_sync();
 }
@@ -549,13 +566,15 @@ __device__ __forceinline__ void scan_item(const FrameDesc& f, int v, uint32_t pi
     const int cx = (int)(pix - (uint32_t)cy * (uint32_t)W);
     const int h = f.h[v];
     uint8_t* Mv = f.M + (size_t)v * H * W;
+    TileView tv{nullptr, f.tiles_x};
+    if (f.tstate) tv.t = f.tstate + (size_t)v * ((H + kTile - 1) / kTile) * f.tiles_x;
     if constexpr (KMAX == 2) {
         if (lanes_per_scanline_k(2 * h + 1) == 1)
-            scanline<1>(f.D, H, W, Mv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, th, L, lane);
+            scanline<1>(f.D, H, W, Mv, tv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, th, L, lane);
         else
-            scanline<2>(f.D, H, W, Mv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, th, L, lane);
+            scanline<2>(f.D, H, W, Mv, tv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, th, L, lane);
     } else {
-        scanline<KMAX>(f.D, H, W, Mv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, th, L, lane);
+        scanline<KMAX>(f.D, H, W, Mv, tv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, th, L, lane);
     }
 }
 
@@ -737,6 +756,9 @@ void describe_frame(FrameDesc* f, const float* D, uint8_t* M, int H, int W, int 
     f->gx = (W + kEdgeCols - 1) / kEdgeCols;
     f->gy = (H + edge_rows - 1) / edge_rows;
     f->block_begin = 0;
+    f->tstate = nullptr;
+    f->tnear = nullptr;
+    f->tiles_x = (W + kTile - 1) / kTile;
     for (int v = 0; v < OCCL_MAX_VIEWS; ++v) {
         f->h[v] = v < n_views ? Ls[v] / 2 : 0;
         f->vord[v] = 0;

@@ -108,6 +108,79 @@ __global__ __launch_bounds__(256) void k_confusion(const uint8_t* __restrict__ p
     }
 }
 
+// ---------------------------------------------------------------------------
+// tile routing
+// ---------------------------------------------------------------------------
+struct RouteViews {
+    float c[OCCL_MAX_VIEWS], s[OCCL_MAX_VIEWS];
+    int h[OCCL_MAX_VIEWS];
+};
+
+__global__ __launch_bounds__(256) void k_route_state(const float* __restrict__ z, long n, float z_lo,
+                                                     float z_hi, uint8_t* __restrict__ st) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const float v = z[i];
+        st[i] = v < z_lo ? 0 : (v > z_hi ? 1 : 2);  // NaN logits take the exact path
+    }
+}
+
+// Can a scanline from a pixel of tile (0, 0) sample a pixel of tile (dx, dy)?
+// A candidate C and its sample p = rint(C + u g), |g| <= h, differ by u g
+// plus at most 1/2 per axis (and fp32 rounding, covered by `slack`), while
+// pixels of the two tiles differ by 16 d +- 15 per axis: the segment
+// {u t : |t| <= h} must meet the box [16 dx +- (15.5 + slack)] x [16 dy +- ...].
+// The test is a superset (it may keep a few candidates that cannot reach).
+__device__ bool tile_reach(int dx, int dy, double c, double s, int h, double slack) {
+    double lo = -(double)h, hi = (double)h;
+    const double half = 15.5 + slack;
+    const double bx0 = 16.0 * dx - half, bx1 = 16.0 * dx + half;
+    const double by0 = 16.0 * dy - half, by1 = 16.0 * dy + half;
+    if (c == 0.0) {
+        if (bx0 > 0.0 || bx1 < 0.0) return false;
+    } else {
+        const double a = bx0 / c, b = bx1 / c;
+        lo = fmax(lo, fmin(a, b));
+        hi = fmin(hi, fmax(a, b));
+    }
+    if (s == 0.0) {
+        if (by0 > 0.0 || by1 < 0.0) return false;
+    } else {
+        const double a = by0 / s, b = by1 / s;
+        lo = fmax(lo, fmin(a, b));
+        hi = fmin(hi, fmax(a, b));
+    }
+    return lo <= hi;
+}
+
+__global__ __launch_bounds__(256) void k_route_near(const uint8_t* __restrict__ st, int n_views,
+                                                    int tiles_y, int tiles_x, RouteViews rv,
+                                                    double slack, uint8_t* __restrict__ near) {
+    const long per = (long)tiles_y * tiles_x;
+    const long n = per * n_views;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const int v = (int)(i / per);
+        const int rem = (int)(i % per);
+        const int ty = rem / tiles_x, tx = rem % tiles_x;
+        const uint8_t* sv = st + (size_t)v * per;
+        const int h = rv.h[v];
+        const int R = (h + 16) / 16 + 1;
+        uint8_t out = 0;
+        for (int dy = -R; dy <= R && !out; ++dy) {
+            const int y = ty + dy;
+            if (y < 0 || y >= tiles_y) continue;
+            for (int dx = -R; dx <= R; ++dx) {
+                const int x = tx + dx;
+                if (x < 0 || x >= tiles_x || sv[(size_t)y * tiles_x + x] != 2) continue;
+                if (tile_reach(dx, dy, rv.c[v], rv.s[v], h, slack)) {
+                    out = 1;
+                    break;
+                }
+            }
+        }
+        near[i] = out;
+    }
+}
+
 inline int grid_for(size_t n, int per_block, int cap) {
     size_t g = (n + per_block - 1) / per_block;
     if (g < 1) g = 1;
@@ -126,6 +199,28 @@ hipError_t launch_scan_stats(hipStream_t st, const float* D, size_t n, uint32_t*
 hipError_t launch_edges_out(hipStream_t st, const float* D, int H, int W, float* E, float* A) {
     const size_t n = (size_t)H * W;
     hipLaunchKernelGGL(k_edges_out, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, D, H, W, E, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_route(hipStream_t st, const float* logits, int n_views, int tiles_y, int tiles_x,
+                        float z_lo, float z_hi, const ViewTable& vt, const int* h, uint8_t* tstate,
+                        uint8_t* tnear) {
+    const size_t n = (size_t)n_views * tiles_y * tiles_x;
+    RouteViews rv{};
+    int hmax = 0;
+    for (int v = 0; v < n_views; ++v) {
+        rv.c[v] = vt.c[v];
+        rv.s[v] = vt.s[v];
+        rv.h[v] = h[v];
+        hmax = h[v] > hmax ? h[v] : hmax;
+    }
+    // fp32 rounding of C + c g: a few ulps of the largest coordinate
+    const double extent = 16.0 * (tiles_x > tiles_y ? tiles_x : tiles_y) + hmax;
+    const double slack = 0.5 + extent * 1.0e-6;
+    hipLaunchKernelGGL(k_route_state, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, logits, (long)n,
+                       z_lo, z_hi, tstate);
+    hipLaunchKernelGGL(k_route_near, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, tstate, n_views,
+                       tiles_y, tiles_x, rv, slack, tnear);
     return hipGetLastError();
 }
 

@@ -418,7 +418,8 @@ extern "C" occl_status occl_profile_read(occl_ctx* ctx, double* ms, int64_t* lau
 // default shape for this frame).
 occl_status occl_ctx::enqueue_frame(const float* D, int H, int W, int n_views, const int* Ls,
                                     const ViewTable& vt, const Thresholds& th, uint8_t* M,
-                                    const TuneConfig* cfg) {
+                                    const TuneConfig* cfg, const uint8_t* tstate,
+                                    const uint8_t* tnear) {
     int maxcls = 0;
     for (int v = 0; v < n_views; ++v) maxcls = std::max(maxcls, scan_class(Ls[v] / 2));
     const TuneConfig tc = cfg ? *cfg : config_for(tune_key(false, (size_t)H * W, n_views, maxcls));
@@ -434,6 +435,8 @@ occl_status occl_ctx::enqueue_frame(const float* D, int H, int W, int n_views, c
     f.lists = (uint32_t*)lists;
     f.counts = (int32_t*)counts;
     f.prefix = (int32_t*)prefix;
+    f.tstate = tstate;
+    f.tnear = tnear;
     hipEvent_t ev = prof_begin(OCCL_STAGE_EDGES);
     hipError_t e = launch_edges(stream, f, n_views, vt, th.q_min);
     if (e != hipSuccess) return hip_fail(e, "edges");
@@ -471,19 +474,25 @@ Thresholds occl::make_thresholds(const occl_params* p) {
     return th;
 }
 
-extern "C" occl_status occl_detect(occl_ctx* ctx, const float* D, int32_t H, int32_t W,
-                                   int32_t n_views, const double* angles_deg, const float* ratios,
-                                   const occl_params* params, uint8_t* M) {
+namespace {
+// occl_detect and occl_detect_routed: validation, view resolution, then the
+// exact path, the exact path routed by the caller's logits, or (USE_CNN)
+// the learned proposal followed by the routed exact path.
+occl_status detect_impl(occl_ctx* ctx, const float* D, int32_t H, int32_t W, int32_t n_views,
+                        const double* angles_deg, const float* ratios, const occl_params* params,
+                        uint8_t* M, bool routed, const float* logits, uint8_t* tile_state) {
     if (!ctx) return OCCL_ERR_INVALID_ARG;
     occl_status s = ctx->check_params(params, n_views, angles_deg, ratios);
     if (s != OCCL_OK) return s;
+    if (routed && !(params->cnn_lo <= params->cnn_hi)) return ctx->fail(OCCL_ERR_INVALID_ARG, "cnn band");
     if (H < 0 || W < 0) return ctx->fail(OCCL_ERR_INVALID_ARG, "negative size");
     if ((size_t)H * (size_t)W > (size_t)1 << 31) return ctx->fail(OCCL_ERR_UNSUPPORTED, "frame too large");
     if ((size_t)H * W == 0 || n_views == 0) return OCCL_OK;
     if (!D || !M) return ctx->fail(OCCL_ERR_INVALID_ARG, "D or M is NULL");
+    if (routed && !logits) return ctx->fail(OCCL_ERR_INVALID_ARG, "logits is NULL");
     if (H > 65535 || W > 65535 * kEdgeCols) return ctx->fail(OCCL_ERR_UNSUPPORTED, "frame too large");
-    if ((params->flags & OCCL_FLAG_USE_CNN) && !ctx->cnn_ready())
-        return ctx->fail(OCCL_ERR_NO_MODEL, "USE_CNN without loaded weights");
+    const bool cnn = !routed && (params->flags & OCCL_FLAG_USE_CNN);
+    if (cnn && !ctx->cnn_ready()) return ctx->fail(OCCL_ERR_NO_MODEL, "USE_CNN without loaded weights");
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return ctx->hip_fail(e, "hipSetDevice");
     ViewTable vt{};
@@ -491,7 +500,9 @@ extern "C" occl_status occl_detect(occl_ctx* ctx, const float* D, int32_t H, int
     s = ctx->resolve_views(D, H, W, n_views, angles_deg, ratios, params, nullptr, &vt, Ls);
     if (s != OCCL_OK) return s;
     const Thresholds th = make_thresholds(params);
-    if (params->flags & OCCL_FLAG_USE_CNN)
+    if (routed)
+        s = ctx->enqueue_routed(D, H, W, n_views, Ls, vt, th, params, logits, M, tile_state);
+    else if (cnn)
         s = ctx->enqueue_frame_cnn(D, H, W, n_views, Ls, vt, th, params, M);
     else
         s = ctx->enqueue_frame(D, H, W, n_views, Ls, vt, th, M, nullptr);
@@ -501,6 +512,20 @@ extern "C" occl_status occl_detect(occl_ctx* ctx, const float* D, int32_t H, int
         if (e != hipSuccess) return ctx->hip_fail(e, "hipStreamSynchronize");
     }
     return OCCL_OK;
+}
+}  // namespace
+
+extern "C" occl_status occl_detect(occl_ctx* ctx, const float* D, int32_t H, int32_t W,
+                                   int32_t n_views, const double* angles_deg, const float* ratios,
+                                   const occl_params* params, uint8_t* M) {
+    return detect_impl(ctx, D, H, W, n_views, angles_deg, ratios, params, M, false, nullptr, nullptr);
+}
+
+extern "C" occl_status occl_detect_routed(occl_ctx* ctx, const float* D, int32_t H, int32_t W,
+                                          int32_t n_views, const double* angles_deg,
+                                          const float* ratios, const occl_params* params,
+                                          const float* logits, uint8_t* M, uint8_t* tile_state) {
+    return detect_impl(ctx, D, H, W, n_views, angles_deg, ratios, params, M, true, logits, tile_state);
 }
 
 extern "C" occl_status occl_last_candidate_counts(occl_ctx* ctx, int64_t* out, int32_t n_views) {

@@ -236,11 +236,6 @@ extern "C" occl_status occl_detect_batched(occl_ctx* ctx, int32_t n_frames, cons
     return OCCL_OK;
 }
 
-occl_status occl_ctx::enqueue_frame_cnn(const float*, int, int, int, const int*, const ViewTable&,
-                                        const Thresholds&, const occl_params*, uint8_t*) {
-    return fail(OCCL_ERR_NO_MODEL, "learned tile proposal not loaded");
-}
-
 // ---------------------------------------------------------------------------
 // autotuner: coordinate search over the launch shape, timed with HIP events
 // on the context's stream on the caller's own data

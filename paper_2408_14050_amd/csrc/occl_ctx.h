@@ -57,8 +57,15 @@ struct occl_ctx {
     std::vector<GraphEntry> graphs;         // most recent first
     int64_t graph_builds = 0, graph_launches = 0;
 
-    // learned tile proposal (k_cnn.hip); weights live in `bufs`
+    // learned tile proposal (k_cnn.hip); weights, Adam moments and
+    // activations live in `bufs`
     bool cnn_loaded = false;
+    int64_t cnn_step = 0;                // Adam steps taken
+    const uint16_t* cnn_act[5] = {};     // outputs of layers 0..4 of the last forward pass
+    int cnn_fwd_n = 0, cnn_fwd_h = 0, cnn_fwd_w = 0;  // its input shape (0: none yet)
+    occl_status cnn_buffers(float** theta, uint16_t** wbf);
+    occl_status cnn_forward(const uint16_t* X, int N, int H, int W, float* Z);
+    occl_status cnn_backward(const uint16_t* X, int N, int H, int W, const float* T, double* loss);
 
     // stage profiling: event pairs per stage, resolved on occl_profile_read
     struct EvPair {
@@ -92,7 +99,8 @@ struct occl_ctx {
                               occl::ViewTable* vt, int* Ls);
     occl_status enqueue_frame(const float* D, int H, int W, int n_views, const int* Ls,
                               const occl::ViewTable& vt, const occl::Thresholds& th, uint8_t* M,
-                              const occl::TuneConfig* cfg);
+                              const occl::TuneConfig* cfg, const uint8_t* tstate = nullptr,
+                              const uint8_t* tnear = nullptr);
     occl_status enqueue_batch(int n_frames, const occl_frame* frames, int n_views, const int* Ls_all,
                               const occl::ViewTable& vt, const occl::Thresholds& th,
                               const occl::TuneConfig* cfg);
@@ -101,4 +109,8 @@ struct occl_ctx {
     occl_status enqueue_frame_cnn(const float* D, int H, int W, int n_views, const int* Ls,
                                   const occl::ViewTable& vt, const occl::Thresholds& th,
                                   const occl_params* p, uint8_t* M);
+    occl_status enqueue_routed(const float* D, int H, int W, int n_views, const int* Ls,
+                               const occl::ViewTable& vt, const occl::Thresholds& th,
+                               const occl_params* p, const float* logits, uint8_t* M,
+                               uint8_t* tile_state);
 };

@@ -91,7 +91,18 @@ struct FrameDesc {
     int h[OCCL_MAX_VIEWS];            // half scan length floor(L/2) per view
     int vord[OCCL_MAX_VIEWS];         // views ordered by scan class (stable)
     int cls_start[kNumClasses + 1];   // number of views of class < ci in vord
+    // Tile routing (NULL on the plain exact path): per view, 16 x 16 pixel
+    // tiles aligned to (0, 0), tiles_x = ceil(W / 16) per row.
+    //   tstate[v][ty][tx]: 0 = fill 0, 1 = fill 1, 2 = exact on this tile
+    //   tnear[v][ty][tx]: 1 if a scanline from a candidate in this tile can
+    //                     sample a tile with state 2 (only such candidates
+    //                     are kept)
+    const uint8_t* tstate;
+    const uint8_t* tnear;
+    int tiles_x;
 };
+
+constexpr int kTile = 16;
 
 // Launch shape chosen by the autotuner.
 struct TuneConfig {
@@ -128,6 +139,12 @@ Thresholds make_thresholds(const occl_params* p);
 hipError_t launch_scan_stats(hipStream_t st, const float* D, size_t n, uint32_t* dev);
 
 hipError_t launch_edges_out(hipStream_t st, const float* D, int H, int W, float* E, float* A);
+
+// Tile routing from logits z [n_views][ty][tx]: state 0 if z < z_lo, 1 if
+// z > z_hi, else 2; then the reach map tnear of the state-2 tiles.
+hipError_t launch_route(hipStream_t st, const float* logits, int n_views, int tiles_y, int tiles_x,
+                        float z_lo, float z_hi, const ViewTable& vt, const int* h, uint8_t* tstate,
+                        uint8_t* tnear);
 
 hipError_t launch_confusion(hipStream_t st, const uint8_t* pred, const uint8_t* ref, size_t n,
                             unsigned long long* dev4);

@@ -90,6 +90,27 @@ _SIGS = {
     "occl_autotune_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(occl_frame), C.c_int32,
                                         C.POINTER(C.c_double), C.POINTER(C.c_float),
                                         C.POINTER(occl_params), C.c_int32, C.POINTER(occl_tune)]),
+    "occl_detect_routed": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                     C.POINTER(C.c_double), C.POINTER(C.c_float),
+                                     C.POINTER(occl_params), C.c_void_p, C.c_void_p, C.c_void_p]),
+    "occl_cnn_num_params": (C.c_size_t, []),
+    "occl_cnn_init": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "occl_cnn_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                     C.c_size_t]),
+    "occl_cnn_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.POINTER(C.c_int64), C.c_size_t]),
+    "occl_cnn_pack": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                C.POINTER(C.c_double), C.POINTER(C.c_float), C.POINTER(C.c_int32),
+                                C.c_void_p]),
+    "occl_cnn_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                   C.c_void_p]),
+    "occl_cnn_activation": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t]),
+    "occl_cnn_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                    C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
+    "occl_cnn_train_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                      C.c_void_p, C.c_float, C.POINTER(C.c_double)]),
+    "occl_cnn_tile_targets": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                        C.c_void_p]),
     "occl_tune_save": (C.c_int, [C.c_void_p, C.c_char_p]),
     "occl_tune_load": (C.c_int, [C.c_void_p, C.c_char_p]),
 }
@@ -269,6 +290,112 @@ class Context:
                                      n.ctypes.data_as(C.POINTER(C.c_int64)))
         self._check(st, "occl_profile_read")
         return {s: (float(ms[i]), int(n[i])) for i, s in enumerate(STAGES)}
+
+    def occl_detect_routed(self, D, angles, ratios, prm: occl_params, logits, M=None,
+                           tile_state=None):
+        """Exact path on the tiles the logits leave uncertain; fills the rest.
+        logits: float32 [V, ceil(H/16), ceil(W/16)] device tensor."""
+        torch = self._torch
+        a, r = self._views(angles, ratios)
+        H, W = int(D.shape[0]), int(D.shape[1])
+        if M is None:
+            M = torch.empty((a.shape[0], H, W), dtype=torch.uint8, device=D.device)
+        st = lib().occl_detect_routed(self.h, _ptr(D), H, W, int(a.shape[0]),
+                                      a.ctypes.data_as(C.POINTER(C.c_double)),
+                                      r.ctypes.data_as(C.POINTER(C.c_float)), C.byref(prm),
+                                      _ptr(logits), _ptr(M), _ptr(tile_state))
+        self._check(st, "occl_detect_routed")
+        return M
+
+    # -- learned tile proposal ----------------------------------------------
+    @staticmethod
+    def occl_cnn_num_params():
+        return int(lib().occl_cnn_num_params())
+
+    def occl_cnn_init(self, seed: int):
+        self._check(lib().occl_cnn_init(self.h, C.c_uint64(int(seed))), "occl_cnn_init")
+
+    def occl_cnn_set_state(self, theta, m=None, v=None, step: int = 0):
+        n = self.occl_cnn_num_params()
+        arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float32) for a in (theta, m, v)]
+        for a in arrs:
+            if a is not None and a.size != n:
+                raise ValueError(f"expected {n} parameters")
+        ptr = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)
+        st = lib().occl_cnn_set_state(self.h, ptr(arrs[0]), ptr(arrs[1]), ptr(arrs[2]), int(step), n)
+        self._check(st, "occl_cnn_set_state")
+
+    def occl_cnn_get_state(self):
+        n = self.occl_cnn_num_params()
+        th, m, v = (np.zeros(n, np.float32) for _ in range(3))
+        step = C.c_int64()
+        st = lib().occl_cnn_get_state(self.h, th.ctypes.data_as(C.c_void_p), m.ctypes.data_as(C.c_void_p),
+                                      v.ctypes.data_as(C.c_void_p), C.byref(step), n)
+        self._check(st, "occl_cnn_get_state")
+        return th, m, v, int(step.value)
+
+    def occl_cnn_pack(self, D, angles, ratios, scan_len, X=None):
+        """Network input of every view: bf16 [V, H, W, 8] (returned as int16 storage)."""
+        torch = self._torch
+        a, r = self._views(angles, ratios)
+        Ls = np.ascontiguousarray(np.atleast_1d(scan_len), dtype=np.int32)
+        H, W = int(D.shape[0]), int(D.shape[1])
+        if X is None:
+            X = torch.empty((a.shape[0], H, W, 8), dtype=torch.int16, device=D.device)
+        st = lib().occl_cnn_pack(self.h, _ptr(D), H, W, int(a.shape[0]),
+                                 a.ctypes.data_as(C.POINTER(C.c_double)),
+                                 r.ctypes.data_as(C.POINTER(C.c_float)),
+                                 Ls.ctypes.data_as(C.POINTER(C.c_int32)), _ptr(X))
+        self._check(st, "occl_cnn_pack")
+        return X
+
+    def occl_cnn_forward(self, X, Z=None):
+        torch = self._torch
+        N, H, W = int(X.shape[0]), int(X.shape[1]), int(X.shape[2])
+        if Z is None:
+            Z = torch.empty((N, (H + 15) // 16, (W + 15) // 16), dtype=torch.float32, device=X.device)
+        st = lib().occl_cnn_forward(self.h, _ptr(X), N, H, W, _ptr(Z))
+        self._check(st, "occl_cnn_forward")
+        return Z
+
+    def occl_cnn_activation(self, layer: int, N: int, H: int, W: int):
+        """Output of hidden layer `layer` of the last forward pass on an
+        [N, H, W, 8] input: bf16 [N, H_l, W_l, 32] (int16 storage)."""
+        torch = self._torch
+        h, w = H, W
+        for l in range(layer + 1):
+            if l < 4:
+                h, w = (h + 1) // 2, (w + 1) // 2
+        out = torch.empty((N, h, w, 32), dtype=torch.int16, device=f"cuda:{self.device}")
+        st = lib().occl_cnn_activation(self.h, int(layer), _ptr(out), out.numel())
+        self._check(st, "occl_cnn_activation")
+        return out
+
+    def occl_cnn_backward(self, X, T, want_grad=True):
+        N, H, W = int(X.shape[0]), int(X.shape[1]), int(X.shape[2])
+        loss = C.c_double()
+        g = np.zeros(self.occl_cnn_num_params(), np.float32) if want_grad else None
+        st = lib().occl_cnn_backward(self.h, _ptr(X), N, H, W, _ptr(T), C.byref(loss),
+                                     None if g is None else g.ctypes.data_as(C.c_void_p))
+        self._check(st, "occl_cnn_backward")
+        return float(loss.value), g
+
+    def occl_cnn_train_step(self, X, T, lr: float, want_loss=True):
+        N, H, W = int(X.shape[0]), int(X.shape[1]), int(X.shape[2])
+        loss = C.c_double()
+        st = lib().occl_cnn_train_step(self.h, _ptr(X), N, H, W, _ptr(T), float(lr),
+                                       C.byref(loss) if want_loss else None)
+        self._check(st, "occl_cnn_train_step")
+        return float(loss.value) if want_loss else None
+
+    def occl_cnn_tile_targets(self, M, T=None):
+        torch = self._torch
+        n, H, W = int(M.shape[0]), int(M.shape[1]), int(M.shape[2])
+        if T is None:
+            T = torch.empty((n, (H + 15) // 16, (W + 15) // 16), dtype=torch.float32, device=M.device)
+        st = lib().occl_cnn_tile_targets(self.h, _ptr(M), n, H, W, _ptr(T))
+        self._check(st, "occl_cnn_tile_targets")
+        return T
 
     def occl_sync(self):
         self._check(lib().occl_sync(self.h), "occl_sync")

@@ -95,7 +95,8 @@ def test_bf16_rounding():
 def test_pack_and_tiles():
     D = np.full((20, 24), 3.0)
     D[5:15, 8:20] = 11.0
-    x = C.pack(D, 45.0, np.float32(1.4142135), 30)
+    c = s = math.cos(math.pi / 4)
+    x = C.pack(D, c, s, np.float32(1.4142135), 30)
     assert np.all(x[..., 4] == C.bf16(np.cos(np.pi / 4))) and np.all(x[..., 7] == 0)
     mag = x[..., 2] ** 2 + x[..., 3] ** 2
     assert np.all(np.abs(mag - 1) < 0.02)
@@ -105,3 +106,23 @@ def test_pack_and_tiles():
     f = C.tile_fraction(M)
     assert f.shape == (2, 3, 3) and f[0].sum() == 0
     assert f[1, 0, 0] == 1.0 and f[1, 1, 0] == 0.5 and f[1, 2, 2] == 0.0
+
+
+def test_pack_angle_channels_are_cos_sin_of_atan2():
+    """Channels 2, 3 are cos and sin of A = atan2(E_y, E_x) of Eq. (1)."""
+    rng = np.random.default_rng(5)
+    D = rng.normal(size=(20, 30)) * 3
+    x = C.pack(D, math.cos(math.pi / 6), 0.5, np.float32(1.0), 10)
+    ex = np.zeros_like(D)
+    ey = np.zeros_like(D)
+    ex[:, :-1] = D[:, 1:] - D[:, :-1]
+    ey[:-1, :] = D[1:, :] - D[:-1, :]
+    A = np.arctan2(ey, ex)
+    assert np.abs(x[..., 2] - C.bf16(np.cos(A))).max() < 1e-15
+    assert np.abs(x[..., 3] - C.bf16(np.sin(A))).max() < 1e-15
+    # last row: E_y = 0, so sin A is exactly 0 and cos A = sign(E_x)
+    assert np.all(x[-1, :, 3] == 0.0)
+    assert np.all(np.abs(x[-1, :-1, 2]) == 1.0)
+    # E = 0 (last pixel): A = atan2(0, 0) = 0
+    assert x[-1, -1, 2] == 1.0 and x[-1, -1, 3] == 0.0
+    np.testing.assert_array_equal(x[..., 1], C.bf16(np.hypot(ex, ey) / 8.0))
