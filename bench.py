@@ -254,6 +254,85 @@ def bench_batched(ctx, steps: int, tune: bool):
             "alg_gbps": round(alg / dt / 1e9, 1), "launch_shape": shape}
 
 
+def cnn_flops(H: int, W: int) -> int:
+    """Multiply-adds x 2 of the tile network's convolutions on one H x W view."""
+    layers = [(8, 32, 2), (32, 32, 2), (32, 32, 2), (32, 32, 2), (32, 32, 1), (32, 1, 1)]
+    tot = 0
+    for ci, co, st in layers:
+        H, W = (H + st - 1) // st, (W + st - 1) // st
+        tot += 2 * H * W * co * 9 * ci
+    return tot
+
+
+def bench_learned(ctx, steps: int, n_eval: int):
+    """Learned tile proposal + exact fallback against the exact path on
+    1920x1080 frames x 8 views (c1 statistics, held-out seeds 4100...)."""
+    import torch
+    from paper_2408_14050_amd import occl, scenes
+    from paper_2408_14050_amd.train_tile_cnn import DEFAULT_WEIGHTS, EVAL_SEED0, load_state
+    meta = load_state(ctx, DEFAULT_WEIGHTS)
+    angles, ratios = scenes.views_3x3()
+    frames = [scenes.make_c1_like(EVAL_SEED0 + k, W=1920, H=1080) for k in range(max(1, n_eval))]
+    bands = [(0.05, 0.95), (0.02, 0.98)]
+    qual = {b: [0, 0, 0, 0, 0] for b in bands}   # tp, fp, fn, exact tiles, tiles
+    for sc in frames:
+        D = torch.from_numpy(sc.D).cuda()
+        M = ctx.occl_detect(D, angles, ratios, occl.params(scan_len_per_view=sc.scan_len))
+        Z = ctx.occl_cnn_forward(ctx.occl_cnn_pack(D, angles, ratios, sc.scan_len))
+        st = torch.empty(Z.shape, dtype=torch.uint8, device="cuda")
+        for b in bands:
+            prm = occl.params(scan_len_per_view=sc.scan_len, cnn_lo=b[0], cnn_hi=b[1],
+                              flags=occl.FLAG_USE_CNN)
+            Mc = ctx.occl_detect(D, angles, ratios, prm)
+            ctx.occl_detect_routed(D, angles, ratios, prm, Z, tile_state=st)
+            c = ctx.occl_confusion(Mc, M)
+            q = qual[b]
+            q[0] += c["tp"]; q[1] += c["fp"]; q[2] += c["fn"]
+            q[3] += int((st == 2).sum().item()); q[4] += st.numel()
+    sc = frames[0]
+    D = torch.from_numpy(sc.D).cuda()
+    M = torch.empty((8, sc.H, sc.W), dtype=torch.uint8, device="cuda")
+    pv = sc.H * sc.W * 8
+
+    def timed(prm):
+        for _ in range(5):
+            ctx.occl_detect(D, angles, ratios, prm, M=M)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.occl_detect(D, angles, ratios, prm, M=M)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        ctx.occl_profile_enable(True)
+        for _ in range(steps):
+            ctx.occl_detect(D, angles, ratios, prm, M=M)
+        pr = ctx.occl_profile_read()
+        ctx.occl_profile_enable(False)
+        stages = {k: round(v[0] / max(1, v[1]), 5) for k, v in pr.items() if v[1]}
+        return dt, stages
+
+    dt_exact, st_exact = timed(occl.params(scan_len_per_view=sc.scan_len))
+    out = {"workload": "c4: 1920x1080 x8 views, c1 statistics, held-out seeds "
+                       f"{EVAL_SEED0}..{EVAL_SEED0 + len(frames) - 1} (timing on the first)",
+           "weights": os.path.relpath(DEFAULT_WEIGHTS, ROOT), "training": meta,
+           "exact": {"ms": round(dt_exact * 1e3, 4), "mpixel_views_per_s": round(pv / dt_exact / 1e6, 1),
+                     "stages_ms": st_exact}}
+    fl = cnn_flops(sc.H, sc.W) * 8
+    for b in bands:
+        prm = occl.params(scan_len_per_view=sc.scan_len, cnn_lo=b[0], cnn_hi=b[1], flags=occl.FLAG_USE_CNN)
+        dt, stages = timed(prm)
+        tp, fp, fn, ex, nt = qual[b]
+        cnn_ms = stages.get("cnn", float("nan"))
+        out[f"cnn_band_{b[0]}_{b[1]}"] = {
+            "ms": round(dt * 1e3, 4), "mpixel_views_per_s": round(pv / dt / 1e6, 1),
+            "vs_exact": round(dt_exact / dt, 4), "iou": round(tp / max(1, tp + fp + fn), 5),
+            "precision": round(tp / max(1, tp + fp), 5), "recall": round(tp / max(1, tp + fn), 5),
+            "exact_tile_share": round(ex / max(1, nt), 5), "stages_ms": stages,
+            "cnn_tflops": round(fl / (cnn_ms * 1e-3) / 1e12, 2) if cnn_ms == cnn_ms else None,
+            "cnn_gflop_per_frame": round(fl / 1e9, 2)}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -269,6 +348,9 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=20)
     ap.add_argument("--profiles-from", default=None, metavar="DIR")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--learned-steps", type=int, default=50)
+    ap.add_argument("--learned-eval", type=int, default=4, help="c4 frames for IoU / P / R")
     args = ap.parse_args()
     if args.copy_probe:
         return copy_probe(args.copy_probe)
@@ -382,6 +464,9 @@ def main() -> int:
 
     if not args.no_batched:
         out["batched"] = bench_batched(ctx, args.batched_steps, not args.no_tune)
+
+    if not args.no_learned:
+        out["learned"] = bench_learned(ctx, args.learned_steps, args.learned_eval)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)

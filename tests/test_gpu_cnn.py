@@ -431,3 +431,23 @@ def test_routed_validates(gctx, torch):
                                       r.ctypes.data_as(C.POINTER(C.c_float)), C.byref(p), None,
                                       _ptr(M), None)
         gctx._check(st, "routed without logits")
+
+
+def test_committed_weights_quality(gctx, torch):
+    """The shipped proposal (trained by train_tile_cnn on 20k crops) on a
+    held-out 1920x1080 frame: IoU of the routed masks against the exact
+    masks (Eq. 7 counts) and the share of tiles that fall back."""
+    from paper_2408_14050_amd import occl
+    from paper_2408_14050_amd.train_tile_cnn import load_state
+    meta = load_state(gctx)
+    assert meta["frames"] * meta["crops_per_frame"] >= 20000
+    angles, ratios = scenes.views_3x3()
+    sc = scenes.make_c1_like(4115, W=1920, H=1080)
+    D = to_dev(torch, sc.D)
+    M = gctx.occl_detect(D, angles, ratios, occl.params(scan_len_per_view=sc.scan_len))
+    prm = occl.params(scan_len_per_view=sc.scan_len, flags=occl.FLAG_USE_CNN | occl.FLAG_SYNC,
+                      cnn_lo=0.02, cnn_hi=0.98)
+    Mc = gctx.occl_detect(D, angles, ratios, prm)
+    c = gctx.occl_confusion(Mc, M)
+    iou = c["tp"] / max(1, c["tp"] + c["fp"] + c["fn"])
+    assert iou >= 0.98, c
