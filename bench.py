@@ -30,14 +30,22 @@ HBM_PEAK_GBPS = 8000.0
 # 32-bit VALU lane operations: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 ALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 PAPER_GPU_MPVS = 1600 * 1200 * 8 / 0.026 / 1e6   # Table 3, RTX 3090, 1600x1200 x 8 directions
-KERNEL_SOURCES = ("paper_2408_14050_amd/csrc/k_exact.hip",)
+CSRC = "paper_2408_14050_amd/csrc/"
 
 
-def kernel_hash() -> str:
+def kernel_source(kernel: str) -> str:
+    if kernel.startswith(("k_conv", "k_pack", "k_bce", "k_adam", "k_wgrad", "k_dgrad")):
+        return CSRC + "k_cnn.hip"
+    if kernel.startswith(("k_route", "k_stats", "k_confusion")):
+        return CSRC + "k_util.hip"
+    return CSRC + "k_exact.hip"
+
+
+def kernel_hash(kernel: str = "k_scanlines") -> str:
+    """First 16 hex digits of the SHA-256 of the kernel's source file."""
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+    with open(os.path.join(ROOT, kernel_source(kernel)), "rb") as f:
+        h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -63,7 +71,7 @@ def traffic_for(kernel: str, workload: str):
     except (OSError, ValueError):
         return None
     e = t.get(kernel, {})
-    if e.get("kernel_hash") != kernel_hash() or e.get("workload") != workload:
+    if e.get("kernel_hash") != kernel_hash(kernel) or e.get("workload") != workload:
         return None
     return e.get("bytes_per_launch")
 
@@ -117,8 +125,12 @@ def cpu_baseline(sc, seconds: float):
 # profiling helpers (run under rocprofv3 on the GPU machine, summarised here)
 # ---------------------------------------------------------------------------
 PROFILE_CMD = ("rocprofv3 {mode} -d gpurun_out/{out} -o run -- python3 bench.py --steps 20 "
-               "--warmup 2 --no-cpu-baseline --no-context --no-check")
+               "--warmup 2 --no-cpu-baseline --no-context --no-check --no-learned")
+LEARNED_PROFILE_CMD = ("rocprofv3 {mode} -d gpurun_out/{out} -o run -- python3 bench.py --learned-only "
+                       "--learned-steps 10 --learned-eval 1")
 BATCH_WORKLOAD = "c3 64 mixed frames seed 3000"
+LEARNED_WORKLOAD = "c4 1920x1080 x8 views seed 4100"
+LEARNED_KERNELS = ("k_pack", "k_conv", "k_route")
 COPY_CMD = "rocprofv3 --pmc {ctr} -d gpurun_out/{out} -o run -- python3 bench.py --copy-probe 256"
 
 
@@ -143,7 +155,7 @@ def _pmc_per_kernel(db_path: str, counter: str):
                        "where counter_name = ? group by name, dispatch_id", (counter,)).fetchall()
     out = {}
     for name, _, val in rows:
-        m = re.search(r"(k_[a-z_0-9]+(<[0-9]+>)?)", name)
+        m = re.search(r"(k_[a-z_0-9]+(<[0-9, ]+>)?)", name)
         key = m.group(1) if m else name.split("(")[0][-40:]
         out.setdefault(key, []).append(val)
     return {k: sum(v) / len(v) for k, v in out.items()}
@@ -160,7 +172,7 @@ def _trace_per_kernel(db_path: str):
     rows = con.execute(f"select {name_col}, start, end from {tab}").fetchall()
     out = {}
     for name, st, en in rows:
-        m = re.search(r"(k_[a-z_0-9]+(<[0-9]+>)?)", name or "")
+        m = re.search(r"(k_[a-z_0-9]+(<[0-9, ]+>)?)", name or "")
         key = m.group(1) if m else (name or "?").split("(")[0][-40:]
         out.setdefault(key, []).append((en - st) / 1e3)
     return {k: {"calls": len(v), "avg_us": sum(v) / len(v), "min_us": min(v), "max_us": max(v)}
@@ -169,15 +181,14 @@ def _trace_per_kernel(db_path: str):
 
 def profiles_from(run_dir: str, workload: str) -> int:
     """Writes profiles/<kernel>__<workload>.txt and profiles/traffic.json from
-    the rocprofv3 databases of one profiling run (trace, FETCH_SIZE and
-    WRITE_SIZE passes of the benchmark, and of the copy probe)."""
+    the rocprofv3 databases of the profiling runs: trace, FETCH_SIZE and
+    WRITE_SIZE passes of the benchmark (prof, pmc_fetch, pmc_write), of its
+    learned section (lprof, lpmc_fetch, lpmc_write; optional) and of the
+    copy probe (copy_fetch, copy_write)."""
     import glob
     def db(sub):
         g = glob.glob(os.path.join(run_dir, sub, "*.db"))
         return g[0] if g else None
-    trace = _trace_per_kernel(db("prof"))
-    fetch = _pmc_per_kernel(db("pmc_fetch"), "FETCH_SIZE")
-    write = _pmc_per_kernel(db("pmc_write"), "WRITE_SIZE")
     cf = _pmc_per_kernel(db("copy_fetch"), "FETCH_SIZE")
     cw = _pmc_per_kernel(db("copy_write"), "WRITE_SIZE")
     copy_kib = 256 * 1024
@@ -187,71 +198,55 @@ def profiles_from(run_dir: str, workload: str) -> int:
                               "write_kib": max(cw.values()) if cw else None,
                               "read_factor": f_read, "write_factor": f_write}}
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
-    for k in sorted(k for k in set(trace) & set(fetch) & set(write) if k.startswith("k_")):
-        wl = BATCH_WORKLOAD if "batched" in k else workload
-        tag = wl.split(":")[0].replace(" ", "_").replace("x8_views", "v8")
-        rd = fetch[k] * 1024 / (f_read or 1.0)
-        wr = write[k] * 1024 / (f_write or 1.0)
-        traffic[k] = {"kernel_hash": kernel_hash(), "workload": wl, "fetch_kib": fetch[k],
-                      "write_kib": write[k], "bytes_per_launch": round(rd + wr),
-                      "read_bytes": round(rd), "write_bytes": round(wr)}
-        lines = [
-            f"# {k} -- {wl}",
-            "",
-            "Commands (from the repository root on the GPU box):",
-            "  " + PROFILE_CMD.format(mode="--kernel-trace --stats", out="prof"),
-            "  " + PROFILE_CMD.format(mode="--pmc FETCH_SIZE", out="pmc_fetch"),
-            "  " + PROFILE_CMD.format(mode="--pmc WRITE_SIZE", out="pmc_write"),
-            "  " + COPY_CMD.format(ctr="FETCH_SIZE", out="copy_fetch"),
-            "  " + COPY_CMD.format(ctr="WRITE_SIZE", out="copy_write"),
-            "  python bench.py --profiles-from gpurun_out   (this summary)",
-            "",
-            f"kernel source hash: {kernel_hash()}",
-            f"dispatches: {trace[k]['calls']}",
-            f"duration avg/min/max (us): {trace[k]['avg_us']:.2f} / {trace[k]['min_us']:.2f} / "
-            f"{trace[k]['max_us']:.2f}",
-            f"FETCH_SIZE per dispatch (KiB): {fetch[k]:.1f}",
-            f"WRITE_SIZE per dispatch (KiB): {write[k]:.1f}",
-            f"copy probe 256 MiB: FETCH_SIZE {traffic['copy_probe']['fetch_kib']} KiB, "
-            f"WRITE_SIZE {traffic['copy_probe']['write_kib']} KiB "
-            f"(read factor {f_read}, write factor {f_write})",
-            f"HBM bytes per dispatch (counters / copy factor): read {rd:.0f}, write {wr:.0f}",
-        ]
-        with open(os.path.join(ROOT, "profiles", f"{k.replace('<', '_').replace('>', '')}__{tag}.txt"), "w") as f:
-            f.write("\n".join(lines) + "\n")
+    runs = [("", PROFILE_CMD, lambda k: not k.startswith(LEARNED_KERNELS)),
+            ("l", LEARNED_PROFILE_CMD, lambda k: k.startswith(LEARNED_KERNELS))]
+    for pre, cmd, keep in runs:
+        if not db(pre + "prof"):
+            continue
+        trace = _trace_per_kernel(db(pre + "prof"))
+        fetch = _pmc_per_kernel(db(pre + "pmc_fetch"), "FETCH_SIZE")
+        write = _pmc_per_kernel(db(pre + "pmc_write"), "WRITE_SIZE")
+        for k in sorted(k for k in set(trace) & set(fetch) & set(write) if k.startswith("k_") and keep(k)):
+            if pre:
+                wl = LEARNED_WORKLOAD
+            else:
+                wl = BATCH_WORKLOAD if "batched" in k else workload
+            tag = wl.split(":")[0].replace(" ", "_").replace("x8_views", "v8")
+            rd = fetch[k] * 1024 / (f_read or 1.0)
+            wr = write[k] * 1024 / (f_write or 1.0)
+            traffic[k] = {"kernel_hash": kernel_hash(k), "source": kernel_source(k), "workload": wl,
+                          "fetch_kib": fetch[k], "write_kib": write[k], "bytes_per_launch": round(rd + wr),
+                          "read_bytes": round(rd), "write_bytes": round(wr),
+                          "avg_us": round(trace[k]["avg_us"], 3)}
+            lines = [
+                f"# {k} -- {wl}",
+                "",
+                "Commands (from the repository root on the GPU box):",
+                "  " + cmd.format(mode="--kernel-trace --stats", out=pre + "prof"),
+                "  " + cmd.format(mode="--pmc FETCH_SIZE", out=pre + "pmc_fetch"),
+                "  " + cmd.format(mode="--pmc WRITE_SIZE", out=pre + "pmc_write"),
+                "  " + COPY_CMD.format(ctr="FETCH_SIZE", out="copy_fetch"),
+                "  " + COPY_CMD.format(ctr="WRITE_SIZE", out="copy_write"),
+                "  python bench.py --profiles-from gpurun_out   (this summary)",
+                "",
+                f"kernel source: {kernel_source(k)} (sha256 prefix {kernel_hash(k)})",
+                f"dispatches: {trace[k]['calls']}",
+                f"duration avg/min/max (us): {trace[k]['avg_us']:.2f} / {trace[k]['min_us']:.2f} / "
+                f"{trace[k]['max_us']:.2f}",
+                f"FETCH_SIZE per dispatch (KiB): {fetch[k]:.1f}",
+                f"WRITE_SIZE per dispatch (KiB): {write[k]:.1f}",
+                f"copy probe 256 MiB: FETCH_SIZE {traffic['copy_probe']['fetch_kib']} KiB, "
+                f"WRITE_SIZE {traffic['copy_probe']['write_kib']} KiB "
+                f"(read factor {f_read}, write factor {f_write})",
+                f"HBM bytes per dispatch (counters / copy factor): read {rd:.0f}, write {wr:.0f}",
+            ]
+            name = k.replace("<", "_").replace(">", "").replace(", ", "_").replace(",", "_")
+            with open(os.path.join(ROOT, "profiles", f"{name}__{tag}.txt"), "w") as f:
+                f.write("\n".join(lines) + "\n")
     with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
         json.dump(traffic, f, indent=1)
     print(json.dumps(traffic, indent=1))
     return 0
-
-
-def bench_batched(ctx, steps: int, tune: bool):
-    """64 frames of mixed size (640x480 .. 2048x1536, c1 statistics, 8 views,
-    per-frame L) in one graph launch per step."""
-    import torch
-    from paper_2408_14050_amd import occl, scenes
-    frames = scenes.make_batch(seed=3000, n_frames=64)
-    Ds = [torch.from_numpy(f.D).cuda() for f in frames]
-    Ms = [torch.empty((f.n_views, f.H, f.W), dtype=torch.uint8, device="cuda") for f in frames]
-    batch = [(D, M, f.scan_len) for D, M, f in zip(Ds, Ms, frames)]
-    prm = occl.params(**frames[0].params)
-    shape = None
-    if tune:
-        shape = ctx.occl_autotune_batched(batch, frames[0].angles, frames[0].ratios, prm, reps=3)
-    for _ in range(3):
-        ctx.occl_detect_batched(batch, frames[0].angles, frames[0].ratios, prm)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        ctx.occl_detect_batched(batch, frames[0].angles, frames[0].ratios, prm)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
-    pv = sum(f.pixel_views for f in frames)
-    alg = sum((4 + f.n_views) * f.H * f.W for f in frames)
-    return {"workload": "c3: 64 frames from {640x480, 1280x960, 1920x1080, 2048x1536}, 8 views, "
-                        "seed 3000", "frames_per_s": round(64 / dt, 1),
-            "ms_per_launch": round(dt * 1e3, 4), "mpixel_views_per_s": round(pv / dt / 1e6, 1),
-            "alg_gbps": round(alg / dt / 1e9, 1), "launch_shape": shape}
 
 
 def cnn_flops(H: int, W: int) -> int:
@@ -349,6 +344,7 @@ def main() -> int:
     ap.add_argument("--batched-steps", type=int, default=20)
     ap.add_argument("--profiles-from", default=None, metavar="DIR")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--learned-only", action="store_true", help="only the learned-path section")
     ap.add_argument("--learned-steps", type=int, default=50)
     ap.add_argument("--learned-eval", type=int, default=4, help="c4 frames for IoU / P / R")
     args = ap.parse_args()
@@ -369,6 +365,11 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
         return 3
+    if args.learned_only:
+        ctx = occl.Context(0)
+        print(json.dumps(bench_learned(ctx, args.learned_steps, args.learned_eval)), flush=True)
+        ctx.occl_release()
+        return 0
     sc = scenes.make_scene("c1", args.seed)
     H, W, V = sc.H, sc.W, sc.n_views
     D = torch.from_numpy(sc.D).cuda()

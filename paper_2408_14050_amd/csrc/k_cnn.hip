@@ -7,15 +7,14 @@
 // (bf16 copy of fp32 master weights), biases fp32; logits fp32 [N][Ht][Wt].
 // Output size of a stride-s layer: ceil(H / s).
 //
-// The 32-output-channel layers are implicit GEMMs on
-// v_mfma_f32_32x32x8_bf16: one wavefront computes 32 output pixels x 32
-// channels; every K step of 8 is one tap (ky, kx) and 8 input channels,
-// i.e. one 16-byte row of the NHWC input (so the A operand of a lane is a
-// single 8-byte load).  Operand layout of the instruction (checked on the
-// device): lane l supplies A[l % 32][4*(l/32) + i] and B[4*(l/32) + i][l % 32],
-// i = 0..3, and accumulator register j of lane l holds
-// D[8*(j/4) + 4*(l/32) + (j%4)][l % 32].
-//   forward  M = output pixels, N = output channels, K = 9 * Cin
+// The 32-output-channel layers are implicit GEMMs on MFMA: one wavefront
+// computes 32 output pixels x 32 channels.  Operand layout of
+// v_mfma_f32_32x32x8_bf16 (checked on the device): lane l supplies
+// A[l % 32][4*(l/32) + i] and B[4*(l/32) + i][l % 32], i = 0..3, and
+// accumulator register j of lane l holds D[8*(j/4) + 4*(l/32) + (j%4)][l % 32];
+// the 32x32x16 form takes 8 consecutive K per lane half the same way.
+//   forward  M = output pixels, N = output channels, K = 9 * Cin (32x32x16;
+//            weights resident in registers, persistent wavefronts)
 //   dgrad    M = input pixels,  N = input channels,  K = 9 * Cout (weights
 //            pre-transposed to [tap][Cin][Cout]; invalid taps of a strided
 //            layer contribute zeros)
@@ -23,13 +22,25 @@
 //            over pixel chunks into FP32 partials that a second kernel sums
 //            in a fixed order (deterministic)
 // The 1-channel last layer and the loss use plain VALU kernels.
+#include <algorithm>
+
 #include "occl_cnn.h"
 
 namespace occl {
 namespace {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// D += A B on v_mfma_f32_32x32x16_bf16: lane l supplies A[l % 32][8*(l/32) + i]
+// and B[8*(l/32) + i][l % 32], i = 0..7 (the accumulator layout is that of
+// the 32x32x8 form)
+__device__ __forceinline__ f32x16 mfma16(s16x8 a, s16x8 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                  __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
     uint32_t u = __float_as_uint(f);
@@ -86,43 +97,59 @@ __global__ __launch_bounds__(256) void k_pack(const float* __restrict__ D, int H
 // ---------------------------------------------------------------------------
 // forward, 32 output channels, bias + ReLU (MFMA implicit GEMM)
 // ---------------------------------------------------------------------------
+// Forward of a 32-output-channel layer, persistent: every wavefront keeps
+// the B operand of all K steps (the whole weight tensor, K = 9 * CIN padded
+// to a multiple of 16) in registers and walks 32-pixel tiles; per tile it
+// issues all A loads (one 16-byte NHWC load per lane per K step), then the
+// MFMA chain, then bias + ReLU + bf16.  K index k = tap * CIN + ci; a K step
+// of 16 is tap k0 / CIN, channels k0 % CIN .. +7 for k0 = 16 s + 8 (l / 32).
 template <int CIN, int S>
-__global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ X,
-                                                  const uint16_t* __restrict__ Wt,
-                                                  const float* __restrict__ bias,
-                                                  uint16_t* __restrict__ Y, int N, int H, int W,
-                                                  int Ho, int Wo) {
+__global__ __launch_bounds__(256) void k_conv_fwd_p(const uint16_t* __restrict__ X,
+                                                    const uint16_t* __restrict__ Wt,
+                                                    const float* __restrict__ bias,
+                                                    uint16_t* __restrict__ Y, int N, int H, int W,
+                                                    int Ho, int Wo) {
+    constexpr int NS = (9 * CIN + 15) / 16;
     const int lane = threadIdx.x & 63;
     const int q = lane >> 5, i32 = lane & 31;
-    const long total = (long)N * Ho * Wo;
-    const long m0 = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 32;
-    if (m0 >= total) return;
-    const long p = m0 + i32;  // the A row this lane loads
-    const bool pv = p < total;
-    const int n = pv ? (int)(p / ((long)Ho * Wo)) : 0;
-    const int rem = pv ? (int)(p % ((long)Ho * Wo)) : 0;
-    const int oy = rem / Wo, ox = rem % Wo;
-    f32x16 acc = {};
+    s16x8 bw[NS];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        const int iy = oy * S + t / 3 - 1, ix = ox * S + t % 3 - 1;
-        const bool in = pv && iy >= 0 && iy < H && ix >= 0 && ix < W;
-        const uint16_t* xrow = X + (((size_t)n * H + (in ? iy : 0)) * W + (in ? ix : 0)) * CIN;
-        const uint16_t* wrow = Wt + ((size_t)i32 * 9 + t) * CIN;
-#pragma unroll
-        for (int cc = 0; cc < CIN / 8; ++cc) {
-            const bf16x4 a = in ? load4(xrow + 8 * cc + 4 * q) : bf16x4{0, 0, 0, 0};
-            const bf16x4 b = load4(wrow + 8 * cc + 4 * q);
-            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
-        }
+    for (int st = 0; st < NS; ++st) {
+        const int k0 = 16 * st + 8 * q;
+        const int tap = k0 / CIN, coff = k0 % CIN;
+        bw[st] = tap < 9 ? *reinterpret_cast<const s16x8*>(Wt + ((size_t)i32 * 9 + tap) * CIN + coff)
+                         : s16x8{0, 0, 0, 0, 0, 0, 0, 0};
     }
     const float bv = bias[i32];
+    const long total = (long)N * Ho * Wo;
+    const long ntiles = (total + 31) / 32;
+    const long step = (long)gridDim.x * (blockDim.x >> 6);
+    for (long tile = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); tile < ntiles; tile += step) {
+        const long p = tile * 32 + i32;  // the A row this lane loads
+        const bool pv = p < total;
+        const int n = pv ? (int)(p / ((long)Ho * Wo)) : 0;
+        const int rem = pv ? (int)(p % ((long)Ho * Wo)) : 0;
+        const int oy = rem / Wo, ox = rem % Wo;
+        s16x8 a[NS];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const long pr = m0 + 8 * (j / 4) + 4 * q + (j % 4);
-        if (pr < total) {
-            const float v = acc[j] + bv;
-            Y[pr * 32 + i32] = f2bf(v > 0.0f ? v : 0.0f);
+        for (int st = 0; st < NS; ++st) {
+            const int k0 = 16 * st + 8 * q;
+            const int tap = k0 / CIN, coff = k0 % CIN;
+            const int iy = oy * S + tap / 3 - 1, ix = ox * S + tap % 3 - 1;
+            const bool in = pv && tap < 9 && iy >= 0 && iy < H && ix >= 0 && ix < W;
+            a[st] = in ? *reinterpret_cast<const s16x8*>(X + (((size_t)n * H + iy) * W + ix) * CIN + coff)
+                       : s16x8{0, 0, 0, 0, 0, 0, 0, 0};
+        }
+        f32x16 acc = {};
+#pragma unroll
+        for (int st = 0; st < NS; ++st) acc = mfma16(a[st], bw[st], acc);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const long pr = tile * 32 + 8 * (j / 4) + 4 * q + (j % 4);
+            if (pr < total) {
+                const float v = acc[j] + bv;
+                Y[pr * 32 + i32] = f2bf(v > 0.0f ? v : 0.0f);
+            }
         }
     }
 }
@@ -440,15 +467,20 @@ hipError_t cnn_pack(hipStream_t st, const float* D, int H, int W, int n_views, c
 }
 
 hipError_t cnn_conv_fwd(hipStream_t st, int cin, int stride, const uint16_t* X, const uint16_t* Wt,
-                        const float* b, uint16_t* Y, int N, int H, int W, int Ho, int Wo) {
-    const long waves = ((long)N * Ho * Wo + 31) / 32;
-    const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
+                        const float* b, uint16_t* Y, int N, int H, int W, int Ho, int Wo, int n_cu) {
+    // persistent: as many 4-wavefront blocks as stay resident (2 wavefronts
+    // per SIMD for the 32-channel forms, whose weights take 72 registers; 4
+    // for the 8-channel form), each wavefront walking 32-pixel tiles with the
+    // weights held in registers
+    const long tiles = ((long)N * Ho * Wo + 31) / 32;
+    const long resident = (long)n_cu * (cin == 8 ? 4 : 2);
+    const dim3 grid((unsigned)std::max<long>(1, std::min<long>((tiles + 3) / 4, resident))), block(256);
     if (cin == 8 && stride == 2)
-        hipLaunchKernelGGL((k_conv_fwd<8, 2>), grid, block, 0, st, X, Wt, b, Y, N, H, W, Ho, Wo);
+        hipLaunchKernelGGL((k_conv_fwd_p<8, 2>), grid, block, 0, st, X, Wt, b, Y, N, H, W, Ho, Wo);
     else if (cin == 32 && stride == 2)
-        hipLaunchKernelGGL((k_conv_fwd<32, 2>), grid, block, 0, st, X, Wt, b, Y, N, H, W, Ho, Wo);
+        hipLaunchKernelGGL((k_conv_fwd_p<32, 2>), grid, block, 0, st, X, Wt, b, Y, N, H, W, Ho, Wo);
     else if (cin == 32 && stride == 1)
-        hipLaunchKernelGGL((k_conv_fwd<32, 1>), grid, block, 0, st, X, Wt, b, Y, N, H, W, Ho, Wo);
+        hipLaunchKernelGGL((k_conv_fwd_p<32, 1>), grid, block, 0, st, X, Wt, b, Y, N, H, W, Ho, Wo);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

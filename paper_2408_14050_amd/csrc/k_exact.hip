@@ -152,6 +152,8 @@ __device__ void finish_frame(const FrameDesc& f, int n_views) {
 // q = E_x^2 + E_y^2 (fp32, same rounding as the definition) is compared with
 // q_min, the smallest fp32 q whose correctly rounded square root exceeds
 // gamma (computed on the host), which is exactly sqrt_rn(q) > gamma.
+constexpr int kViewChunk = 8;
+
 __device__ void edge_block(const FrameDesc& f, int bx, int by, int n_views, const ViewTable& vt,
                            float q_min) {
     const float* __restrict__ D = f.D;
@@ -202,35 +204,59 @@ __device__ void edge_block(const FrameDesc& f, int bx, int by, int n_views, cons
         }
         if (__ballot(any)) {
             const int band = by / f.ll.block_rows_per_copy;
-            for (int v = 0; v < n_views; ++v) {
-                const float c = vt.c[v], s = vt.s[v];
-                // routed frames keep only candidates that can reach an exact tile
-                // (x0 .. x0 + 3 share one tile)
-                const bool near =
-                    !f.tnear || (live && f.tnear[((size_t)v * ((H + kTile - 1) / kTile) + y / kTile) *
-                                                     f.tiles_x + x0 / kTile]);
-                uint64_t b[4];
-                int m4 = 0;
+            const uint32_t pix = (uint32_t)y * (uint32_t)W + (uint32_t)x0;
+            // Views go in chunks of kViewChunk: the candidate bits of every view
+            // of the chunk first, then one atomic instruction in which lane i
+            // reserves view v0 + i's entries (a single round trip for the
+            // chunk), then the appends.
+            for (int v0 = 0; v0 < n_views; v0 += kViewChunk) {
+                uint32_t m4all = 0;  // bit 4 i + j: pixel x0 + j is a candidate of view v0 + i
+                int tot[kViewChunk], off[kViewChunk];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float dot = __fadd_rn(__fmul_rn(ex[j], c), __fmul_rn(ey[j], s));
-                    const bool cand = strong[j] && (dot > 0.0f) && near;
-                    m4 |= cand ? (1 << j) : 0;
-                    b[j] = __ballot(cand);
+                for (int i = 0; i < kViewChunk; ++i) {
+                    tot[i] = 0;
+                    off[i] = 0;
+                    const int v = v0 + i;
+                    if (v >= n_views) continue;  // uniform
+                    const float c = vt.c[v], s = vt.s[v];
+                    // routed frames keep only candidates that can reach an exact
+                    // tile (x0 .. x0 + 3 share one tile)
+                    const bool near =
+                        !f.tnear || (live && f.tnear[((size_t)v * ((H + kTile - 1) / kTile) + y / kTile) *
+                                                         f.tiles_x + x0 / kTile]);
+                    uint64_t b[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float dot = __fadd_rn(__fmul_rn(ex[j], c), __fmul_rn(ey[j], s));
+                        const bool cand = strong[j] && (dot > 0.0f) && near;
+                        m4all |= cand ? (1u << (4 * i + j)) : 0u;
+                        b[j] = __ballot(cand);
+                    }
+                    tot[i] = __popcll(b[0]) + __popcll(b[1]) + __popcll(b[2]) + __popcll(b[3]);
+                    off[i] = (int)(lanes_below(b[0]) + lanes_below(b[1]) + lanes_below(b[2]) +
+                                   lanes_below(b[3]));
                 }
-                const int tot = __popcll(b[0]) + __popcll(b[1]) + __popcll(b[2]) + __popcll(b[3]);
-                if (tot == 0) continue;
-                const int off = (int)(lanes_below(b[0]) + lanes_below(b[1]) + lanes_below(b[2]) +
-                                      lanes_below(b[3]));
-                const int seg = v * f.ll.copies + band;
-                int base = 0;
-                if (lane == 0) base = atomicAdd(&f.counts[seg * kCounterPad], tot);
-                base = __builtin_amdgcn_readlane(base, 0);
-                uint32_t* dst = f.lists + (size_t)seg * f.ll.cap + base + off;
-                const uint32_t pix = (uint32_t)y * (uint32_t)W + (uint32_t)x0;
+                int my_tot = 0;
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (m4 & (1 << j)) *dst++ = pix + j;
+                for (int i = 0; i < kViewChunk; ++i) my_tot = (lane == i) ? tot[i] : my_tot;
+                int my_base = 0;
+                if (my_tot > 0)
+                    my_base = atomicAdd(&f.counts[((v0 + lane) * f.ll.copies + band) * kCounterPad], my_tot);
+                // every base into a scalar before the first append (the appends'
+                // stores would otherwise sit between the atomic and its reads)
+                int bs[kViewChunk];
+#pragma unroll
+                for (int i = 0; i < kViewChunk; ++i) bs[i] = __builtin_amdgcn_readlane(my_base, i);
+#pragma unroll
+                for (int i = 0; i < kViewChunk; ++i) {
+                    if (tot[i] == 0) continue;
+                    const int seg = (v0 + i) * f.ll.copies + band;
+                    uint32_t* dst = f.lists + (size_t)seg * f.ll.cap + bs[i] + off[i];
+                    const uint32_t m4 = m4all >> (4 * i);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (m4 & (1u << j)) *dst++ = pix + j;
+                }
             }
         }
         if (live) {

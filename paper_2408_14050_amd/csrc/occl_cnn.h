@@ -18,7 +18,7 @@ void cnn_dims(int H, int W, int* Hs, int* Ws);
 hipError_t cnn_pack(hipStream_t st, const float* D, int H, int W, int n_views, const ViewTable& vt,
                     const int* Ls, uint16_t* X);
 hipError_t cnn_conv_fwd(hipStream_t st, int cin, int stride, const uint16_t* X, const uint16_t* Wt,
-                        const float* b, uint16_t* Y, int N, int H, int W, int Ho, int Wo);
+                        const float* b, uint16_t* Y, int N, int H, int W, int Ho, int Wo, int n_cu);
 hipError_t cnn_conv_last(hipStream_t st, const uint16_t* X, const uint16_t* Wt, const float* b,
                          float* Z, int N, int H, int W);
 hipError_t cnn_bce(hipStream_t st, const float* Z, const float* T, float* dZ, double* partial, long n,

@@ -74,7 +74,7 @@ occl_status occl_ctx::cnn_forward(const uint16_t* X, int N, int H, int W, float*
         const size_t o = off_w(l);
         hipError_t e = cnn_conv_fwd(stream, kLayers[l].cin, kLayers[l].stride, in, wbf + o,
                                     theta + o + (size_t)32 * 9 * kLayers[l].cin, (uint16_t*)out, N,
-                                    Hs[l], Ws[l], Hs[l + 1], Ws[l + 1]);
+                                    Hs[l], Ws[l], Hs[l + 1], Ws[l + 1], n_cu);
         if (e != hipSuccess) return hip_fail(e, "cnn conv fwd");
         cnn_act[l] = (uint16_t*)out;
         in = (const uint16_t*)out;
