@@ -211,9 +211,19 @@ occl_status occl_cnn_pack(occl_ctx* ctx, const float* D, int32_t H, int32_t W, i
 occl_status occl_cnn_forward(occl_ctx* ctx, const uint16_t* X, int32_t N, int32_t H, int32_t W,
                              float* logits);
 
+/* The proposal of one frame: logits of every view straight from D (device
+ * fp32 [H][W]) into device fp32 logits [n_views][ceil(H/16)][ceil(W/16)].
+ * The input packing is fused into the first layer; the logits are
+ * bit-identical to occl_cnn_pack followed by occl_cnn_forward with the same
+ * views and scan lengths (host int32 [n_views] >= 1).  Needs weights. */
+occl_status occl_cnn_propose(occl_ctx* ctx, const float* D, int32_t H, int32_t W, int32_t n_views,
+                             const double* angles_deg, const float* ratios, const int32_t* scan_len,
+                             float* logits);
+
 /* Copies the output of hidden layer `layer` (0..4) of the most recent
- * forward pass (occl_cnn_forward, _backward, _train_step or a USE_CNN
- * detection) into dst: device bf16 [N][H_l][W_l][32] with n =
+ * forward pass (occl_cnn_forward, _backward, _train_step, _propose or a
+ * USE_CNN detection; the last two keep no layer-0 output: OCCL_ERR_STATE)
+ * into dst: device bf16 [N][H_l][W_l][32] with n =
  * N * H_l * W_l * 32 elements (H_l = H halved, rounding up, once per
  * stride-2 layer up to `layer`).  For inspection and tests. */
 occl_status occl_cnn_activation(occl_ctx* ctx, int32_t layer, uint16_t* dst, size_t n);

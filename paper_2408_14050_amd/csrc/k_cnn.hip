@@ -42,13 +42,39 @@ __device__ __forceinline__ f32x16 mfma16(s16x8 a, s16x8 b, f32x16 c) {
                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
-__device__ __forceinline__ uint16_t f2bf(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return 0x7fc0;  // NaN
-    u += 0x7fffu + ((u >> 16) & 1u);                                            // nearest, ties to even
-    return (uint16_t)(u >> 16);
+
+// fp32 -> bf16, round to nearest, ties to even: gfx950's v_cvt_pk_bf16_f32
+// (checked on the device against the integer rounding rule on 2^25 bit
+// patterns, every finite value class included)
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
 }
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// The forward kernels run the MFMA with the weights as A (rows = output
+// channels) and the pixels as B, so accumulator register 4 g + i of lane l
+// holds output channel 8 g + 4 (l / 32) + i of pixel l % 32: a lane owns 16
+// channels of one pixel, in four runs of 4.  relu_pack turns run g into 4
+// bf16 (bias added, ReLU).
+__device__ __forceinline__ uint2 relu_pack(const f32x16& acc, const float (&bias)[16], int g) {
+    float v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float x = acc[4 * g + i] + bias[4 * g + i];
+        v[i] = x > 0.0f ? x : 0.0f;
+    }
+    return uint2{pk_bf16(v[0], v[1]), pk_bf16(v[2], v[3])};
+}
+
+__device__ __forceinline__ void load_bias16(const float* __restrict__ b, int q, float (&out)[16]) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[4 * g + i] = b[8 * g + 4 * q + i];
+}
 
 __device__ __forceinline__ bf16x4 load4(const uint16_t* p) {
     return *reinterpret_cast<const bf16x4*>(p);
@@ -94,38 +120,252 @@ __global__ __launch_bounds__(256) void k_pack(const float* __restrict__ D, int H
     }
 }
 
+// The view-independent part of the input, once per frame: G[i] = {D (fp32
+// bits), bf16 E/8, bf16 cos A | bf16 sin A << 16, 0}, computed exactly as
+// k_pack computes those channels.
+__global__ __launch_bounds__(256) void k_pack_base(const float* __restrict__ D, int H, int W,
+                                                   uint4* __restrict__ G) {
+    const size_t HW = (size_t)H * W;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < HW;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int y = (int)(i / W), x = (int)(i % W);
+        const float d = D[i];
+        const float ex = (x + 1 < W) ? D[i + 1] - d : 0.0f;
+        const float ey = (y + 1 < H) ? D[i + W] - d : 0.0f;
+        const float E = sqrtf(ex * ex + ey * ey);
+        const float ca = E > 0.0f ? ex / E : 1.0f;
+        const float sa = E > 0.0f ? ey / E : 0.0f;
+        G[i] = uint4{__float_as_uint(d), (uint32_t)f2bf(E * 0.125f),
+                     (uint32_t)f2bf(ca) | ((uint32_t)f2bf(sa) << 16), 0u};
+    }
+}
+
+// First layer (8 -> 32, stride 2) of every view straight from G: the packed
+// input of view v at a tap pixel is {bf16(D r / L), E/8, cos A, sin A,
+// cos alpha, sin alpha, r/2, 0} (bit-identical to k_pack's), assembled in
+// registers, so the 16-byte-per-pixel-per-view input never goes to memory.
+// Each wavefront loads a tile's G values once and runs the MFMA chain of
+// every view on them.  Output NHWC bf16 [n_views][Ho][Wo][32].
+__global__ __launch_bounds__(256) void k_conv0_fused(const uint4* __restrict__ G, int H, int W,
+                                                     int n_views, PackViews pv,
+                                                     const uint16_t* __restrict__ Wt,
+                                                     const float* __restrict__ bias,
+                                                     uint16_t* __restrict__ Y, int Ho, int Wo) {
+    constexpr int CIN = 8, NS = 5;
+    __shared__ s16x8 wl[NS * 2 * 32];
+    for (int i = threadIdx.x; i < NS * 64; i += blockDim.x) {
+        const int st = i / 64, qq = (i / 32) % 2, co = i % 32;
+        const int tap = 2 * st + qq;
+        wl[i] = tap < 9 ? *reinterpret_cast<const s16x8*>(Wt + ((size_t)co * 9 + tap) * CIN)
+                        : s16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int q = lane >> 5, i32 = lane & 31;
+    float bv[16];
+    load_bias16(bias, q, bv);
+    const long total = (long)Ho * Wo;  // per view
+    const long ntiles = (total + 31) / 32;
+    const long step = (long)gridDim.x * (blockDim.x >> 6);
+    for (long tile = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); tile < ntiles; tile += step) {
+        const long p = tile * 32 + i32;
+        const bool pvalid = p < total;
+        const int oy = pvalid ? (int)(p / Wo) : 0, ox = pvalid ? (int)(p % Wo) : 0;
+        uint4 g[NS];
+        bool in[NS];
+#pragma unroll
+        for (int st = 0; st < NS; ++st) {
+            const int tap = 2 * st + q;
+            const int iy = oy * 2 + tap / 3 - 1, ix = ox * 2 + tap % 3 - 1;
+            in[st] = pvalid && tap < 9 && iy >= 0 && iy < H && ix >= 0 && ix < W;
+            g[st] = in[st] ? G[(size_t)iy * W + ix] : uint4{0u, 0u, 0u, 0u};
+        }
+        for (int v = 0; v < n_views; ++v) {
+            const float r = pv.r[v], il = pv.inv_L[v];
+            const uint32_t w2 = (uint32_t)f2bf(pv.c[v]) | ((uint32_t)f2bf(pv.s[v]) << 16);
+            const uint32_t w3 = (uint32_t)f2bf(r * 0.5f);
+            int z;
+            asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+            f32x16 acc = {};
+#pragma unroll
+            for (int st = 0; st < NS; ++st) {
+                const uint32_t ch0 = f2bf(__uint_as_float(g[st].x) * r * il);
+                const uint4 w = in[st] ? uint4{ch0 | (g[st].y << 16), g[st].z, w2, w3} : uint4{0u, 0u, 0u, 0u};
+                acc = mfma16(wl[st * 64 + lane + z], __builtin_bit_cast(s16x8, w), acc);
+            }
+            if (pvalid) {
+                uint16_t* yp = Y + ((size_t)v * total + p) * 32 + 4 * q;
+#pragma unroll
+                for (int g = 0; g < 4; ++g) *reinterpret_cast<uint2*>(yp + 8 * g) = relu_pack(acc, bv, g);
+            }
+        }
+    }
+}
+
+// Layers 0 and 1 of every view fused, straight from G.  A block owns an
+// output tile of layer 1 (TY rows x 32 columns).  It stages the G values
+// under the tile (4 TY + 3 rows x 131 columns) in LDS once for all views;
+// per view it computes the layer-0 outputs under the tile (2 TY + 1 rows x
+// 65 columns, zero outside the layer-0 image) into LDS, then layer 1 from
+// LDS, so layer 0's output (the largest tensor of the network) never goes to
+// memory.  The layer-0 tile is stored by column parity ([row][parity]
+// [column / 2][32 channels]), so the stride-2 taps of layer 1 read
+// consecutive entries across lanes (entries padded to 80 bytes to spread
+// the LDS banks).  Layer-1 weights stay in
+// registers for all views of the tile, layer-0 weights in LDS.  The
+// arithmetic (K order, roundings) is that of k_conv0_fused followed by
+// k_conv_fwd_p<32, 2>, so the result is identical.
+template <int TY>
+__global__ __launch_bounds__(64 * TY) void k_conv01_fused(
+    const uint4* __restrict__ G, int H, int W, int n_views, PackViews pv,
+    const uint16_t* __restrict__ W0, const float* __restrict__ b0, const uint16_t* __restrict__ W1,
+    const float* __restrict__ b1, uint16_t* __restrict__ Y1, int H0, int W0n, int H1, int W1n) {
+    constexpr int TX = 32;
+    constexpr int R0 = 2 * TY + 1, C0 = 2 * TX + 1;
+    constexpr int CE = TX + 1;        // entries per (row, parity)
+    constexpr int NP0 = R0 * C0;      // layer-0 pixels of the tile
+    constexpr int NT0 = (NP0 + 31) / 32;
+    constexpr int RG = 2 * R0 + 1, CG = 2 * C0 + 1;  // G window
+    constexpr int ES = 40;            // entry stride in bf16: 80 bytes, an odd number of 16-byte
+                                      // slots, so neighbouring entries fall on different banks
+    __shared__ uint16_t l0[R0 * 2 * CE * ES];
+    __shared__ float gsd[RG * CG];    // D of the G window
+    __shared__ uint2 gse[RG * CG];    // {E/8, cos A | sin A << 16} of the G window
+    __shared__ s16x8 wl0[5 * 64];
+    for (int i = threadIdx.x; i < 5 * 64; i += blockDim.x) {
+        const int st = i / 64, qq = (i / 32) % 2, co = i % 32;
+        const int tap = 2 * st + qq;
+        wl0[i] = tap < 9 ? *reinterpret_cast<const s16x8*>(W0 + ((size_t)co * 9 + tap) * 8)
+                         : s16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    }
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int q = lane >> 5, i32 = lane & 31;
+    s16x8 bw[18];
+#pragma unroll
+    for (int st = 0; st < 18; ++st) {
+        const int k0 = 16 * st + 8 * q;
+        bw[st] = *reinterpret_cast<const s16x8*>(W1 + ((size_t)i32 * 9 + k0 / 32) * 32 + k0 % 32);
+    }
+    float bv0[16], bv1[16];
+    load_bias16(b0, q, bv0);
+    load_bias16(b1, q, bv1);
+    const int tiles_x = (W1n + TX - 1) / TX, tiles_y = (H1 + TY - 1) / TY;
+    for (int tile = blockIdx.x; tile < tiles_x * tiles_y; tile += gridDim.x) {
+        const int Ya = (tile / tiles_x) * TY, Xa = (tile % tiles_x) * TX;
+        const int gy0 = 2 * Ya - 1, gx0 = 2 * Xa - 1;  // layer-0 coordinates of the tile's (0, 0)
+        const int dy0 = 2 * gy0 - 1, dx0 = 2 * gx0 - 1;  // frame coordinates of the G window's (0, 0)
+        __syncthreads();  // the previous tile's readers of gs are done
+        for (int i = threadIdx.x; i < RG * CG; i += blockDim.x) {
+            const int iy = dy0 + i / CG, ix = dx0 + i % CG;
+            const uint4 g = (iy >= 0 && iy < H && ix >= 0 && ix < W) ? G[(size_t)iy * W + ix]
+                                                                     : uint4{0u, 0u, 0u, 0u};
+            gsd[i] = __uint_as_float(g.x);
+            gse[i] = uint2{g.y, g.z};
+        }
+        __syncthreads();
+        for (int v = 0; v < n_views; ++v) {
+            const float r = pv.r[v], il = pv.inv_L[v];
+            const uint32_t w2 = (uint32_t)f2bf(pv.c[v]) | ((uint32_t)f2bf(pv.s[v]) << 16);
+            const uint32_t w3 = (uint32_t)f2bf(r * 0.5f);
+            // ---- layer 0 into LDS ----
+            for (int t0 = wave; t0 < NT0; t0 += TY) {
+                const int p = t0 * 32 + i32;
+                const int r0 = p / C0, c0 = p % C0;
+                const int gy = gy0 + r0, gx = gx0 + c0;
+                const bool inimg = p < NP0 && gy >= 0 && gy < H0 && gx >= 0 && gx < W0n;
+                int z;
+                asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+                f32x16 acc = {};
+#pragma unroll
+                for (int st = 0; st < 5; ++st) {
+                    const int tap = 2 * st + q;
+                    const int ky = tap / 3, kx = tap % 3;
+                    const int iy = 2 * gy + ky - 1, ix = 2 * gx + kx - 1;
+                    const bool in = inimg && tap < 9 && iy >= 0 && iy < H && ix >= 0 && ix < W;
+                    uint4 w = uint4{0u, 0u, 0u, 0u};
+                    if (in) {
+                        const int gi = (2 * r0 + ky) * CG + 2 * c0 + kx;
+                        const uint2 ge = gse[gi];
+                        const uint32_t ch0 = f2bf(gsd[gi] * r * il);
+                        w = uint4{ch0 | (ge.x << 16), ge.y, w2, w3};
+                    }
+                    acc = mfma16(wl0[st * 64 + lane + z], __builtin_bit_cast(s16x8, w), acc);
+                }
+                if (p < NP0) {
+                    // this lane's pixel (r0, c0): 16 channels, zero outside the layer-0 image
+                    const int e = (r0 * 2 + (c0 & 1)) * CE + (c0 >> 1);
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        const uint2 v2 = inimg ? relu_pack(acc, bv0, g) : uint2{0u, 0u};
+                        *reinterpret_cast<uint2*>(l0 + e * ES + 8 * g + 4 * q) = v2;
+                    }
+                }
+            }
+            __syncthreads();
+            // ---- layer 1 from LDS: wavefront `wave` takes output row Ya + wave ----
+            {
+                const int ly = wave, lx = i32;
+                int z;
+                asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+                f32x16 acc = {};
+#pragma unroll
+                for (int st = 0; st < 18; ++st) {
+                    const int k0 = 16 * st + 8 * q;
+                    const int tap = k0 / 32, coff = k0 % 32;
+                    const int ky = tap / 3, kx = tap % 3;
+                    const int e = ((2 * ly + ky) * 2 + (kx & 1)) * CE + lx + (kx >> 1);
+                    const s16x8 a = *reinterpret_cast<const s16x8*>(l0 + e * ES + coff + z);
+                    acc = mfma16(bw[st], a, acc);
+                }
+                const int Yo = Ya + ly, xo = Xa + lx;
+                if (Yo < H1 && xo < W1n) {
+                    uint16_t* yp = Y1 + (((size_t)v * H1 + Yo) * W1n + xo) * 32 + 4 * q;
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) *reinterpret_cast<uint2*>(yp + 8 * g) = relu_pack(acc, bv1, g);
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // forward, 32 output channels, bias + ReLU (MFMA implicit GEMM)
 // ---------------------------------------------------------------------------
-// Forward of a 32-output-channel layer, persistent: every wavefront keeps
-// the B operand of all K steps (the whole weight tensor, K = 9 * CIN padded
-// to a multiple of 16) in registers and walks 32-pixel tiles; per tile it
-// issues all A loads (one 16-byte NHWC load per lane per K step), then the
-// MFMA chain, then bias + ReLU + bf16.  K index k = tap * CIN + ci; a K step
-// of 16 is tap k0 / CIN, channels k0 % CIN .. +7 for k0 = 16 s + 8 (l / 32).
+// Forward of a 32-output-channel layer, persistent: the block stages the B
+// operand of all K steps (the whole weight tensor, K = 9 * CIN padded to a
+// multiple of 16) in LDS once, laid out so that a K step's fragment is one
+// conflict-free 16-byte read per lane; every wavefront then walks 32-pixel
+// tiles, issuing all A loads of a tile (one 16-byte NHWC load per lane per K
+// step) before its MFMA chain, then bias + ReLU + bf16.  K index
+// k = tap * CIN + ci; a K step of 16 is tap k0 / CIN, channels k0 % CIN .. +7
+// for k0 = 16 s + 8 (l / 32).
 template <int CIN, int S>
-__global__ __launch_bounds__(256) void k_conv_fwd_p(const uint16_t* __restrict__ X,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_conv_fwd_p(const uint16_t* __restrict__ X,
                                                     const uint16_t* __restrict__ Wt,
                                                     const float* __restrict__ bias,
                                                     uint16_t* __restrict__ Y, int N, int H, int W,
                                                     int Ho, int Wo) {
     constexpr int NS = (9 * CIN + 15) / 16;
+    __shared__ s16x8 wl[NS * 2 * 32];  // [step][lane half][output channel]
+    for (int i = threadIdx.x; i < NS * 64; i += blockDim.x) {
+        const int st = i / 64, qq = (i / 32) % 2, co = i % 32;
+        const int k0 = 16 * st + 8 * qq;
+        const int tap = k0 / CIN, coff = k0 % CIN;
+        wl[i] = tap < 9 ? *reinterpret_cast<const s16x8*>(Wt + ((size_t)co * 9 + tap) * CIN + coff)
+                        : s16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    }
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     const int q = lane >> 5, i32 = lane & 31;
-    s16x8 bw[NS];
-#pragma unroll
-    for (int st = 0; st < NS; ++st) {
-        const int k0 = 16 * st + 8 * q;
-        const int tap = k0 / CIN, coff = k0 % CIN;
-        bw[st] = tap < 9 ? *reinterpret_cast<const s16x8*>(Wt + ((size_t)i32 * 9 + tap) * CIN + coff)
-                         : s16x8{0, 0, 0, 0, 0, 0, 0, 0};
-    }
-    const float bv = bias[i32];
+    float bv[16];
+    load_bias16(bias, q, bv);
     const long total = (long)N * Ho * Wo;
     const long ntiles = (total + 31) / 32;
     const long step = (long)gridDim.x * (blockDim.x >> 6);
     for (long tile = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); tile < ntiles; tile += step) {
-        const long p = tile * 32 + i32;  // the A row this lane loads
+        const long p = tile * 32 + i32;  // this lane's pixel
         const bool pv = p < total;
         const int n = pv ? (int)(p / ((long)Ho * Wo)) : 0;
         const int rem = pv ? (int)(p % ((long)Ho * Wo)) : 0;
@@ -140,16 +380,17 @@ __global__ __launch_bounds__(256) void k_conv_fwd_p(const uint16_t* __restrict__
             a[st] = in ? *reinterpret_cast<const s16x8*>(X + (((size_t)n * H + iy) * W + ix) * CIN + coff)
                        : s16x8{0, 0, 0, 0, 0, 0, 0, 0};
         }
+        // an opaque zero keeps the weight reads inside the loop (hoisted, they
+        // would hold 72 registers and halve the resident wavefronts)
+        int z;
+        asm volatile("s_mov_b32 %0, 0" : "=s"(z));
         f32x16 acc = {};
 #pragma unroll
-        for (int st = 0; st < NS; ++st) acc = mfma16(a[st], bw[st], acc);
+        for (int st = 0; st < NS; ++st) acc = mfma16(wl[st * 64 + lane + z], a[st], acc);
+        if (pv) {
+            uint16_t* yp = Y + p * 32 + 4 * q;
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const long pr = tile * 32 + 8 * (j / 4) + 4 * q + (j % 4);
-            if (pr < total) {
-                const float v = acc[j] + bv;
-                Y[pr * 32 + i32] = f2bf(v > 0.0f ? v : 0.0f);
-            }
+            for (int g = 0; g < 4; ++g) *reinterpret_cast<uint2*>(yp + 8 * g) = relu_pack(acc, bv, g);
         }
     }
 }
@@ -468,12 +709,10 @@ hipError_t cnn_pack(hipStream_t st, const float* D, int H, int W, int n_views, c
 
 hipError_t cnn_conv_fwd(hipStream_t st, int cin, int stride, const uint16_t* X, const uint16_t* Wt,
                         const float* b, uint16_t* Y, int N, int H, int W, int Ho, int Wo, int n_cu) {
-    // persistent: as many 4-wavefront blocks as stay resident (2 wavefronts
-    // per SIMD for the 32-channel forms, whose weights take 72 registers; 4
-    // for the 8-channel form), each wavefront walking 32-pixel tiles with the
-    // weights held in registers
+    // persistent: as many 4-wavefront blocks as stay resident, each wavefront
+    // walking 32-pixel tiles
     const long tiles = ((long)N * Ho * Wo + 31) / 32;
-    const long resident = (long)n_cu * (cin == 8 ? 4 : 2);
+    const long resident = (long)n_cu * (cin == 8 ? 8 : 4);
     const dim3 grid((unsigned)std::max<long>(1, std::min<long>((tiles + 3) / 4, resident))), block(256);
     if (cin == 8 && stride == 2)
         hipLaunchKernelGGL((k_conv_fwd_p<8, 2>), grid, block, 0, st, X, Wt, b, Y, N, H, W, Ho, Wo);
@@ -483,6 +722,44 @@ hipError_t cnn_conv_fwd(hipStream_t st, int cin, int stride, const uint16_t* X, 
         hipLaunchKernelGGL((k_conv_fwd_p<32, 1>), grid, block, 0, st, X, Wt, b, Y, N, H, W, Ho, Wo);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t cnn_first_layer_fused(hipStream_t st, const float* D, int H, int W, int n_views,
+                                 const ViewTable& vt, const int* Ls, uint4* G, const uint16_t* Wt,
+                                 const float* b, uint16_t* Y, int Ho, int Wo, int n_cu) {
+    PackViews pv{};
+    for (int v = 0; v < n_views; ++v) {
+        pv.c[v] = vt.c[v];
+        pv.s[v] = vt.s[v];
+        pv.r[v] = vt.r[v];
+        pv.inv_L[v] = 1.0f / (float)Ls[v];
+    }
+    hipLaunchKernelGGL(k_pack_base, dim3(blocks_for((long)H * W, 256, 16384)), dim3(256), 0, st, D, H, W, G);
+    const long tiles = ((long)Ho * Wo + 31) / 32;
+    const dim3 grid((unsigned)std::max<long>(1, std::min<long>((tiles + 3) / 4, (long)n_cu * 8)));
+    hipLaunchKernelGGL(k_conv0_fused, grid, dim3(256), 0, st, G, H, W, n_views, pv, Wt, b, Y, Ho, Wo);
+    return hipGetLastError();
+}
+
+hipError_t cnn_first_layers_fused(hipStream_t st, const float* D, int H, int W, int n_views,
+                                  const ViewTable& vt, const int* Ls, uint4* G, const uint16_t* W0,
+                                  const float* b0, const uint16_t* W1, const float* b1, uint16_t* Y1,
+                                  int H0, int W0n, int H1, int W1n, int n_cu) {
+    PackViews pv{};
+    for (int v = 0; v < n_views; ++v) {
+        pv.c[v] = vt.c[v];
+        pv.s[v] = vt.s[v];
+        pv.r[v] = vt.r[v];
+        pv.inv_L[v] = 1.0f / (float)Ls[v];
+    }
+    hipLaunchKernelGGL(k_pack_base, dim3(blocks_for((long)H * W, 256, 16384)), dim3(256), 0, st, D, H, W, G);
+    constexpr int TY = 8;
+    const long tiles = (long)((H1 + TY - 1) / TY) * ((W1n + 31) / 32);
+    // one block per compute unit (its LDS holds the G window and the layer-0 tile)
+    const dim3 grid((unsigned)std::max<long>(1, std::min<long>(tiles, (long)n_cu)));
+    hipLaunchKernelGGL(k_conv01_fused<TY>, grid, dim3(64 * TY), 0, st, G, H, W, n_views, pv, W0, b0, W1, b1,
+                       Y1, H0, W0n, H1, W1n);
     return hipGetLastError();
 }
 

@@ -152,30 +152,49 @@ __device__ bool tile_reach(int dx, int dy, double c, double s, int h, double sla
     return lo <= hi;
 }
 
-__global__ __launch_bounds__(256) void k_route_near(const uint8_t* __restrict__ st, int n_views,
-                                                    int tiles_y, int tiles_x, RouteViews rv,
-                                                    double slack, uint8_t* __restrict__ near) {
+// The reach stencil of each view: the tile offsets (dx, dy), |dx|, |dy| <= R,
+// that pass tile_reach, as packed (dy << 16 | dx & 0xffff) entries.
+// One block per view; entries [v * cap, v * cap + count[v]).
+__global__ __launch_bounds__(256) void k_route_stencil(RouteViews rv, double slack, int cap,
+                                                       int* __restrict__ count, int* __restrict__ st) {
+    __shared__ int n;
+    const int v = blockIdx.x;
+    const int h = rv.h[v];
+    const int R = (h + 16) / 16 + 1;
+    const int side = 2 * R + 1;
+    if (threadIdx.x == 0) n = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < side * side; i += blockDim.x) {
+        const int dx = i % side - R, dy = i / side - R;
+        if (tile_reach(dx, dy, rv.c[v], rv.s[v], h, slack)) {
+            const int k = atomicAdd(&n, 1);
+            if (k < cap) st[(size_t)v * cap + k] = (int)(((unsigned)dy << 16) | ((unsigned)dx & 0xffffu));
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) count[v] = n < cap ? n : cap;
+}
+
+__global__ __launch_bounds__(256) void k_route_near(const uint8_t* __restrict__ state, int n_views,
+                                                    int tiles_y, int tiles_x, int cap,
+                                                    const int* __restrict__ count,
+                                                    const int* __restrict__ stencil,
+                                                    uint8_t* __restrict__ near) {
     const long per = (long)tiles_y * tiles_x;
     const long n = per * n_views;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         const int v = (int)(i / per);
         const int rem = (int)(i % per);
         const int ty = rem / tiles_x, tx = rem % tiles_x;
-        const uint8_t* sv = st + (size_t)v * per;
-        const int h = rv.h[v];
-        const int R = (h + 16) / 16 + 1;
+        const uint8_t* sv = state + (size_t)v * per;
+        const int* sl = stencil + (size_t)v * cap;
+        const int m = count[v];
         uint8_t out = 0;
-        for (int dy = -R; dy <= R && !out; ++dy) {
-            const int y = ty + dy;
-            if (y < 0 || y >= tiles_y) continue;
-            for (int dx = -R; dx <= R; ++dx) {
-                const int x = tx + dx;
-                if (x < 0 || x >= tiles_x || sv[(size_t)y * tiles_x + x] != 2) continue;
-                if (tile_reach(dx, dy, rv.c[v], rv.s[v], h, slack)) {
-                    out = 1;
-                    break;
-                }
-            }
+        for (int k = 0; k < m && !out; ++k) {
+            const int e = sl[k];
+            const int dx = (int)(short)(e & 0xffff), dy = e >> 16;
+            const int x = tx + dx, y = ty + dy;
+            out = (x >= 0 && x < tiles_x && y >= 0 && y < tiles_y && sv[(size_t)y * tiles_x + x] == 2) ? 1 : 0;
         }
         near[i] = out;
     }
@@ -202,9 +221,16 @@ hipError_t launch_edges_out(hipStream_t st, const float* D, int H, int W, float*
     return hipGetLastError();
 }
 
+int route_stencil_cap(const int* h, int n_views) {
+    int hmax = 0;
+    for (int v = 0; v < n_views; ++v) hmax = h[v] > hmax ? h[v] : hmax;
+    const int R = (hmax + 16) / 16 + 1;
+    return (2 * R + 1) * (2 * R + 1);
+}
+
 hipError_t launch_route(hipStream_t st, const float* logits, int n_views, int tiles_y, int tiles_x,
                         float z_lo, float z_hi, const ViewTable& vt, const int* h, uint8_t* tstate,
-                        uint8_t* tnear) {
+                        uint8_t* tnear, int* stencil_ws) {
     const size_t n = (size_t)n_views * tiles_y * tiles_x;
     RouteViews rv{};
     int hmax = 0;
@@ -219,8 +245,12 @@ hipError_t launch_route(hipStream_t st, const float* logits, int n_views, int ti
     const double slack = 0.5 + extent * 1.0e-6;
     hipLaunchKernelGGL(k_route_state, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, logits, (long)n,
                        z_lo, z_hi, tstate);
+    const int cap = route_stencil_cap(h, n_views);
+    int* count = stencil_ws;
+    int* sten = stencil_ws + OCCL_MAX_VIEWS;
+    hipLaunchKernelGGL(k_route_stencil, dim3(n_views), dim3(256), 0, st, rv, slack, cap, count, sten);
     hipLaunchKernelGGL(k_route_near, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, tstate, n_views,
-                       tiles_y, tiles_x, rv, slack, tnear);
+                       tiles_y, tiles_x, cap, count, sten, tnear);
     return hipGetLastError();
 }
 

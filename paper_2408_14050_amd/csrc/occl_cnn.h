@@ -19,6 +19,17 @@ hipError_t cnn_pack(hipStream_t st, const float* D, int H, int W, int n_views, c
                     const int* Ls, uint16_t* X);
 hipError_t cnn_conv_fwd(hipStream_t st, int cin, int stride, const uint16_t* X, const uint16_t* Wt,
                         const float* b, uint16_t* Y, int N, int H, int W, int Ho, int Wo, int n_cu);
+// Layer 0 of every view straight from D (input packing fused; bit-identical
+// to cnn_pack followed by cnn_conv_fwd).  G: workspace of H * W uint4.
+hipError_t cnn_first_layer_fused(hipStream_t st, const float* D, int H, int W, int n_views,
+                                 const ViewTable& vt, const int* Ls, uint4* G, const uint16_t* Wt,
+                                 const float* b, uint16_t* Y, int Ho, int Wo, int n_cu);
+// Layers 0 and 1 of every view straight from D, layer 0 never leaving LDS
+// (bit-identical to cnn_pack, then cnn_conv_fwd twice).
+hipError_t cnn_first_layers_fused(hipStream_t st, const float* D, int H, int W, int n_views,
+                                  const ViewTable& vt, const int* Ls, uint4* G, const uint16_t* W0,
+                                  const float* b0, const uint16_t* W1, const float* b1, uint16_t* Y1,
+                                  int H0, int W0n, int H1, int W1n, int n_cu);
 hipError_t cnn_conv_last(hipStream_t st, const uint16_t* X, const uint16_t* Wt, const float* b,
                          float* Z, int N, int H, int W);
 hipError_t cnn_bce(hipStream_t st, const float* Z, const float* T, float* dZ, double* partial, long n,

@@ -57,15 +57,16 @@ occl_status occl_ctx::cnn_buffers(float** theta, uint16_t** wbf) {
 
 // Forward pass of N samples of H x W x 8 (bf16 NHWC); logits to Z [N][Ht][Wt].
 // Activations stay in the context workspace for a following backward pass.
-occl_status occl_ctx::cnn_forward(const uint16_t* X, int N, int H, int W, float* Z) {
+// Layers first..5 on the input `in` of layer `first` (N samples of an H x W
+// network input); logits to Z.  Activations stay in the context workspace.
+occl_status occl_ctx::cnn_layers(int first, const uint16_t* in, int N, int H, int W, float* Z) {
     float* theta;
     uint16_t* wbf;
     occl_status s = cnn_buffers(&theta, &wbf);
     if (s != OCCL_OK) return s;
     int Hs[kCnnLayers + 1], Ws[kCnnLayers + 1];
     cnn_dims(H, W, Hs, Ws);
-    const uint16_t* in = X;
-    for (int l = 0; l < kCnnLayers - 1; ++l) {
+    for (int l = first; l < kCnnLayers - 1; ++l) {
         char name[16];
         std::snprintf(name, sizeof(name), "cnn_a%d", l);
         void* out;
@@ -86,6 +87,37 @@ occl_status occl_ctx::cnn_forward(const uint16_t* X, int N, int H, int W, float*
     cnn_fwd_h = H;
     cnn_fwd_w = W;
     return OCCL_OK;
+}
+
+// Forward pass of N samples of H x W x 8 (bf16 NHWC); logits to Z [N][Ht][Wt].
+occl_status occl_ctx::cnn_forward(const uint16_t* X, int N, int H, int W, float* Z) {
+    return cnn_layers(0, X, N, H, W, Z);
+}
+
+// The proposal of a frame: every view's logits straight from D (layer 0
+// reads D through the per-frame base planes; bit-identical to packing every
+// view and running cnn_forward).
+occl_status occl_ctx::cnn_forward_frame(const float* D, int H, int W, int n_views, const ViewTable& vt,
+                                        const int* Ls, float* Z) {
+    float* theta;
+    uint16_t* wbf;
+    occl_status s = cnn_buffers(&theta, &wbf);
+    if (s != OCCL_OK) return s;
+    int Hs[kCnnLayers + 1], Ws[kCnnLayers + 1];
+    cnn_dims(H, W, Hs, Ws);
+    void *G, *a1;
+    s = ensure("cnn_g", (size_t)H * W * sizeof(uint4), &G);
+    if (s == OCCL_OK) s = ensure("cnn_a1", (size_t)n_views * Hs[2] * Ws[2] * 32 * sizeof(uint16_t), &a1);
+    if (s != OCCL_OK) return s;
+    const size_t o1 = off_w(1);
+    hipError_t e = cnn_first_layers_fused(stream, D, H, W, n_views, vt, Ls, (uint4*)G, wbf,
+                                          theta + (size_t)32 * 9 * kCnnInCh, wbf + o1,
+                                          theta + o1 + (size_t)32 * 9 * 32, (uint16_t*)a1, Hs[1], Ws[1],
+                                          Hs[2], Ws[2], n_cu);
+    if (e != hipSuccess) return hip_fail(e, "cnn first layers");
+    cnn_act[0] = nullptr;  // layer 0's output never leaves LDS
+    cnn_act[1] = (const uint16_t*)a1;
+    return cnn_layers(2, (const uint16_t*)a1, n_views, H, W, Z);
 }
 
 // Loss (mean soft BCE against T) and the gradient of every parameter into
@@ -233,6 +265,8 @@ extern "C" occl_status occl_cnn_activation(occl_ctx* ctx, int32_t layer, uint16_
     if (!ctx) return OCCL_ERR_INVALID_ARG;
     if (layer < 0 || layer >= kCnnLayers - 1 || !dst) return ctx->fail(OCCL_ERR_INVALID_ARG, "layer / dst");
     if (ctx->cnn_fwd_n == 0) return ctx->fail(OCCL_ERR_STATE, "no forward pass yet");
+    if (!ctx->cnn_act[layer])
+        return ctx->fail(OCCL_ERR_STATE, "layer not kept by the last forward pass (fused proposal)");
     int Hs[kCnnLayers + 1], Ws[kCnnLayers + 1];
     cnn_dims(ctx->cnn_fwd_h, ctx->cnn_fwd_w, Hs, Ws);
     const size_t want = (size_t)ctx->cnn_fwd_n * Hs[layer + 1] * Ws[layer + 1] * 32;
@@ -262,6 +296,27 @@ extern "C" occl_status occl_cnn_pack(occl_ctx* ctx, const float* D, int32_t H, i
     hipError_t e = cnn_pack(ctx->stream, D, H, W, n_views, vt, scan_len, X);
     if (e != hipSuccess) return ctx->hip_fail(e, "cnn pack");
     return OCCL_OK;
+}
+
+extern "C" occl_status occl_cnn_propose(occl_ctx* ctx, const float* D, int32_t H, int32_t W,
+                                        int32_t n_views, const double* angles_deg, const float* ratios,
+                                        const int32_t* scan_len, float* logits) {
+    occl_status s = check_ctx_model(ctx);
+    if (s != OCCL_OK) return s;
+    if (!D || !logits || !scan_len || !angles_deg || !ratios || H < 1 || W < 1 || n_views < 1 ||
+        n_views > OCCL_MAX_VIEWS || (long)H * W > (1l << 31))
+        return ctx->fail(OCCL_ERR_INVALID_ARG, "propose arguments");
+    ViewTable vt{};
+    int Ls[OCCL_MAX_VIEWS];
+    for (int v = 0; v < n_views; ++v) {
+        if (scan_len[v] < 1 || !(ratios[v] > 0.0f) || !std::isfinite(ratios[v]) || !std::isfinite(angles_deg[v]))
+            return ctx->fail(OCCL_ERR_INVALID_ARG, "propose view");
+        occl_direction(angles_deg[v], &vt.c[v], &vt.s[v]);
+        vt.r[v] = ratios[v];
+        Ls[v] = scan_len[v];
+    }
+    (void)hipSetDevice(ctx->device);
+    return ctx->cnn_forward_frame(D, H, W, n_views, vt, Ls, logits);
 }
 
 extern "C" occl_status occl_cnn_tile_targets(occl_ctx* ctx, const uint8_t* M, int32_t n, int32_t H,
@@ -342,16 +397,20 @@ occl_status occl_ctx::enqueue_routed(const float* D, int H, int W, int n_views, 
                                      const float* logits, uint8_t* M, uint8_t* tile_state) {
     const int ty = (H + kTile - 1) / kTile, tx = (W + kTile - 1) / kTile;
     const size_t nt = (size_t)n_views * ty * tx;
-    void *st = tile_state, *near;
+    int h[OCCL_MAX_VIEWS];
+    for (int v = 0; v < n_views; ++v) h[v] = Ls[v] / 2;
+    void *st = tile_state, *near, *sten;
     occl_status s = OCCL_OK;
     if (!st) s = ensure("tile_state", nt, &st);
     if (s == OCCL_OK) s = ensure("tile_near", nt, &near);
+    if (s == OCCL_OK)
+        s = ensure("tile_stencil",
+                   ((size_t)OCCL_MAX_VIEWS + (size_t)n_views * route_stencil_cap(h, n_views)) * sizeof(int),
+                   &sten);
     if (s != OCCL_OK) return s;
-    int h[OCCL_MAX_VIEWS];
-    for (int v = 0; v < n_views; ++v) h[v] = Ls[v] / 2;
     hipEvent_t ev = prof_begin(OCCL_STAGE_FALLBACK);
     hipError_t e = launch_route(stream, logits, n_views, ty, tx, logit_bound(p->cnn_lo),
-                                logit_bound(p->cnn_hi), vt, h, (uint8_t*)st, (uint8_t*)near);
+                                logit_bound(p->cnn_hi), vt, h, (uint8_t*)st, (uint8_t*)near, (int*)sten);
     if (e != hipSuccess) return hip_fail(e, "route");
     s = enqueue_frame(D, H, W, n_views, Ls, vt, th, M, nullptr, (const uint8_t*)st, (const uint8_t*)near);
     if (s != OCCL_OK) return s;
@@ -363,14 +422,11 @@ occl_status occl_ctx::enqueue_frame_cnn(const float* D, int H, int W, int n_view
                                         const ViewTable& vt, const Thresholds& th, const occl_params* p,
                                         uint8_t* M) {
     const int ty = (H + kTile - 1) / kTile, tx = (W + kTile - 1) / kTile;
-    void *X, *Z;
-    occl_status s = ensure("cnn_x", (size_t)n_views * H * W * kCnnInCh * sizeof(uint16_t), &X);
-    if (s == OCCL_OK) s = ensure("cnn_logits", (size_t)n_views * ty * tx * sizeof(float), &Z);
+    void* Z;
+    occl_status s = ensure("cnn_logits", (size_t)n_views * ty * tx * sizeof(float), &Z);
     if (s != OCCL_OK) return s;
     hipEvent_t ev = prof_begin(OCCL_STAGE_CNN);
-    hipError_t e = cnn_pack(stream, D, H, W, n_views, vt, Ls, (uint16_t*)X);
-    if (e != hipSuccess) return hip_fail(e, "cnn pack");
-    s = cnn_forward((const uint16_t*)X, n_views, H, W, (float*)Z);
+    s = cnn_forward_frame(D, H, W, n_views, vt, Ls, (float*)Z);
     if (s != OCCL_OK) return s;
     prof_end(OCCL_STAGE_CNN, ev);
     return enqueue_routed(D, H, W, n_views, Ls, vt, th, p, (const float*)Z, M, nullptr);

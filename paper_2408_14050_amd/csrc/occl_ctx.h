@@ -64,7 +64,10 @@ struct occl_ctx {
     const uint16_t* cnn_act[5] = {};     // outputs of layers 0..4 of the last forward pass
     int cnn_fwd_n = 0, cnn_fwd_h = 0, cnn_fwd_w = 0;  // its input shape (0: none yet)
     occl_status cnn_buffers(float** theta, uint16_t** wbf);
+    occl_status cnn_layers(int first, const uint16_t* in, int N, int H, int W, float* Z);
     occl_status cnn_forward(const uint16_t* X, int N, int H, int W, float* Z);
+    occl_status cnn_forward_frame(const float* D, int H, int W, int n_views, const occl::ViewTable& vt,
+                                  const int* Ls, float* Z);
     occl_status cnn_backward(const uint16_t* X, int N, int H, int W, const float* T, double* loss);
 
     // stage profiling: event pairs per stage, resolved on occl_profile_read

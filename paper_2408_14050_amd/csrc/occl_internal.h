@@ -141,10 +141,13 @@ hipError_t launch_scan_stats(hipStream_t st, const float* D, size_t n, uint32_t*
 hipError_t launch_edges_out(hipStream_t st, const float* D, int H, int W, float* E, float* A);
 
 // Tile routing from logits z [n_views][ty][tx]: state 0 if z < z_lo, 1 if
-// z > z_hi, else 2; then the reach map tnear of the state-2 tiles.
+// z > z_hi, else 2; then the reach map tnear of the state-2 tiles through a
+// per-view stencil of tile offsets.  stencil_ws: device workspace of
+// OCCL_MAX_VIEWS + n_views * route_stencil_cap(h, n_views) ints.
+int route_stencil_cap(const int* h, int n_views);
 hipError_t launch_route(hipStream_t st, const float* logits, int n_views, int tiles_y, int tiles_x,
                         float z_lo, float z_hi, const ViewTable& vt, const int* h, uint8_t* tstate,
-                        uint8_t* tnear);
+                        uint8_t* tnear, int* stencil_ws);
 
 hipError_t launch_confusion(hipStream_t st, const uint8_t* pred, const uint8_t* ref, size_t n,
                             unsigned long long* dev4);

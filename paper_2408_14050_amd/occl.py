@@ -104,6 +104,9 @@ _SIGS = {
                                 C.c_void_p]),
     "occl_cnn_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
                                    C.c_void_p]),
+    "occl_cnn_propose": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                   C.POINTER(C.c_double), C.POINTER(C.c_float), C.POINTER(C.c_int32),
+                                   C.c_void_p]),
     "occl_cnn_activation": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t]),
     "occl_cnn_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
                                     C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
@@ -356,6 +359,22 @@ class Context:
             Z = torch.empty((N, (H + 15) // 16, (W + 15) // 16), dtype=torch.float32, device=X.device)
         st = lib().occl_cnn_forward(self.h, _ptr(X), N, H, W, _ptr(Z))
         self._check(st, "occl_cnn_forward")
+        return Z
+
+    def occl_cnn_propose(self, D, angles, ratios, scan_len, Z=None):
+        """Logits [V, ceil(H/16), ceil(W/16)] of every view straight from D."""
+        torch = self._torch
+        a, r = self._views(angles, ratios)
+        Ls = np.ascontiguousarray(np.atleast_1d(scan_len), dtype=np.int32)
+        H, W = int(D.shape[0]), int(D.shape[1])
+        if Z is None:
+            Z = torch.empty((a.shape[0], (H + 15) // 16, (W + 15) // 16), dtype=torch.float32,
+                            device=D.device)
+        st = lib().occl_cnn_propose(self.h, _ptr(D), H, W, int(a.shape[0]),
+                                    a.ctypes.data_as(C.POINTER(C.c_double)),
+                                    r.ctypes.data_as(C.POINTER(C.c_float)),
+                                    Ls.ctypes.data_as(C.POINTER(C.c_int32)), _ptr(Z))
+        self._check(st, "occl_cnn_propose")
         return Z
 
     def occl_cnn_activation(self, layer: int, N: int, H: int, W: int):

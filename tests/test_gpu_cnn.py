@@ -451,3 +451,29 @@ def test_committed_weights_quality(gctx, torch):
     c = gctx.occl_confusion(Mc, M)
     iou = c["tp"] / max(1, c["tp"] + c["fp"] + c["fn"])
     assert iou >= 0.98, c
+
+
+@pytest.mark.parametrize("shape", [(192, 256), (61, 83), (1080, 1920), (17, 300), (1, 1)])
+def test_propose_equals_pack_then_forward(gctx, torch, shape):
+    """occl_cnn_propose (packing fused into the first layer, all views per
+    tile) gives the same logits, bit for bit, as packing every view and
+    running the network on the packed input."""
+    H, W = shape
+    rng = np.random.default_rng(H + W)
+    gctx.occl_cnn_set_state(rand_theta(rng))
+    D = rng.uniform(0, 30, size=(H, W)).astype(np.float32)
+    D[H // 4:H // 2, W // 3:W // 2] += 12.0
+    Dt = to_dev(torch, D)
+    angles = np.array([0.0, 45.0, 90.0, 135.0, 200.0, 333.0])
+    ratios = np.array([1.0, 1.4142135, 1.0, 1.4142135, 0.8, 2.5], np.float32)
+    Ls = np.array([33, 48, 51, 70, 20, 120], np.int32)
+    from paper_2408_14050_amd import occl
+    Z1 = gctx.occl_cnn_propose(Dt, angles, ratios, Ls).cpu().numpy()
+    a1 = gctx.occl_cnn_activation(1, 6, H, W).cpu().numpy()
+    with pytest.raises(occl.OcclError):  # layer 0 stays in LDS on this path
+        gctx.occl_cnn_activation(0, 6, H, W)
+    X = gctx.occl_cnn_pack(Dt, angles, ratios, Ls)
+    Z2 = gctx.occl_cnn_forward(X).cpu().numpy()
+    b1 = gctx.occl_cnn_activation(1, 6, H, W).cpu().numpy()
+    np.testing.assert_array_equal(a1, b1)
+    np.testing.assert_array_equal(Z1, Z2)
