@@ -269,36 +269,44 @@ __global__ __launch_bounds__(64 * TY) void k_conv01_fused(
             const uint32_t w2 = (uint32_t)f2bf(pv.c[v]) | ((uint32_t)f2bf(pv.s[v]) << 16);
             const uint32_t w3 = (uint32_t)f2bf(r * 0.5f);
             // ---- layer 0 into LDS ----
+            // Out-of-frame G entries are zero, so channels 0-3 of an outside tap
+            // are already 0 and only the constant channels need masking; tap 9
+            // (K padding) has zero weights and reads any in-window entry.
             for (int t0 = wave; t0 < NT0; t0 += TY) {
                 const int p = t0 * 32 + i32;
-                const int r0 = p / C0, c0 = p % C0;
+                const int pc = p < NP0 ? p : NP0 - 1;
+                const int r0 = pc / C0, c0 = pc % C0;
                 const int gy = gy0 + r0, gx = gx0 + c0;
                 const bool inimg = p < NP0 && gy >= 0 && gy < H0 && gx >= 0 && gx < W0n;
+                const int fy = 2 * gy - 1, fx = 2 * gx - 1;  // frame coordinates of tap (0, 0)
+                bool rok[3], cok[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    rok[k] = fy + k >= 0 && fy + k < H;
+                    cok[k] = fx + k >= 0 && fx + k < W;
+                }
+                const int gbase = 2 * r0 * CG + 2 * c0;
                 int z;
                 asm volatile("s_mov_b32 %0, 0" : "=s"(z));
                 f32x16 acc = {};
 #pragma unroll
                 for (int st = 0; st < 5; ++st) {
-                    const int tap = 2 * st + q;
-                    const int ky = tap / 3, kx = tap % 3;
-                    const int iy = 2 * gy + ky - 1, ix = 2 * gx + kx - 1;
-                    const bool in = inimg && tap < 9 && iy >= 0 && iy < H && ix >= 0 && ix < W;
-                    uint4 w = uint4{0u, 0u, 0u, 0u};
-                    if (in) {
-                        const int gi = (2 * r0 + ky) * CG + 2 * c0 + kx;
-                        const uint2 ge = gse[gi];
-                        const uint32_t ch0 = f2bf(gsd[gi] * r * il);
-                        w = uint4{ch0 | (ge.x << 16), ge.y, w2, w3};
-                    }
+                    const int ta = 2 * st, tb = 2 * st + 1 < 9 ? 2 * st + 1 : 0;  // lane half 0 / 1
+                    const int gi = gbase + (q ? (tb / 3) * CG + tb % 3 : (ta / 3) * CG + ta % 3);
+                    const bool in = q ? (2 * st + 1 < 9 && rok[tb / 3] && cok[tb % 3])
+                                      : (rok[ta / 3] && cok[ta % 3]);
+                    const uint2 ge = gse[gi];
+                    const uint32_t ch0 = f2bf(gsd[gi] * r * il);
+                    const uint4 w = uint4{ch0 | (ge.x << 16), ge.y, in ? w2 : 0u, in ? w3 : 0u};
                     acc = mfma16(wl0[st * 64 + lane + z], __builtin_bit_cast(s16x8, w), acc);
                 }
                 if (p < NP0) {
                     // this lane's pixel (r0, c0): 16 channels, zero outside the layer-0 image
-                    const int e = (r0 * 2 + (c0 & 1)) * CE + (c0 >> 1);
+                    uint16_t* dst = l0 + ((r0 * 2 + (c0 & 1)) * CE + (c0 >> 1)) * ES + 4 * q;
 #pragma unroll
                     for (int g = 0; g < 4; ++g) {
-                        const uint2 v2 = inimg ? relu_pack(acc, bv0, g) : uint2{0u, 0u};
-                        *reinterpret_cast<uint2*>(l0 + e * ES + 8 * g + 4 * q) = v2;
+                        const uint2 v2 = relu_pack(acc, bv0, g);
+                        *reinterpret_cast<uint2*>(dst + 8 * g) = inimg ? v2 : uint2{0u, 0u};
                     }
                 }
             }
@@ -308,15 +316,14 @@ __global__ __launch_bounds__(64 * TY) void k_conv01_fused(
                 const int ly = wave, lx = i32;
                 int z;
                 asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+                // lane base (column lx, channel half q) + a per-step constant
+                const uint16_t* lb = l0 + (2 * ly * 2 * CE + lx) * ES + 8 * q + z;
                 f32x16 acc = {};
 #pragma unroll
                 for (int st = 0; st < 18; ++st) {
-                    const int k0 = 16 * st + 8 * q;
-                    const int tap = k0 / 32, coff = k0 % 32;
-                    const int ky = tap / 3, kx = tap % 3;
-                    const int e = ((2 * ly + ky) * 2 + (kx & 1)) * CE + lx + (kx >> 1);
-                    const s16x8 a = *reinterpret_cast<const s16x8*>(l0 + e * ES + coff + z);
-                    acc = mfma16(bw[st], a, acc);
+                    const int tap = st / 2, ky = tap / 3, kx = tap % 3;
+                    const int off = ((ky * 2 + (kx & 1)) * CE + (kx >> 1)) * ES + 16 * (st % 2);
+                    acc = mfma16(bw[st], *reinterpret_cast<const s16x8*>(lb + off), acc);
                 }
                 const int Yo = Ya + ly, xo = Xa + lx;
                 if (Yo < H1 && xo < W1n) {

@@ -78,34 +78,66 @@ __global__ __launch_bounds__(256) void k_edges_out(const float* __restrict__ D, 
     }
 }
 
-__global__ void k_zero_u64(unsigned long long* p, int n) {
-    if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+// Confusion counts: per-block partial TP / FP / FN (16 mask bytes per lane
+// per step), then one block sums the partials in a fixed order; TN = n minus
+// the other three.  No atomics, so the result is deterministic.
+__device__ __forceinline__ uint32_t nz_bits(uint32_t w) {  // bit b: byte b of w is nonzero
+    return (uint32_t)((w & 0xffu) != 0) | ((uint32_t)((w & 0xff00u) != 0) << 1) |
+           ((uint32_t)((w & 0xff0000u) != 0) << 2) | ((uint32_t)((w & 0xff000000u) != 0) << 3);
 }
 
 __global__ __launch_bounds__(256) void k_confusion(const uint8_t* __restrict__ pred,
                                                    const uint8_t* __restrict__ ref, size_t n,
-                                                   unsigned long long* __restrict__ out) {
-    unsigned long long tp = 0, fp = 0, fn = 0, tn = 0;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+                                                   unsigned long long* __restrict__ partial) {
+    __shared__ unsigned long long red[3][4];
+    unsigned long long tp = 0, fp = 0, fn = 0;
+    const bool vec = ((reinterpret_cast<uintptr_t>(pred) | reinterpret_cast<uintptr_t>(ref)) & 15) == 0;
+    const size_t nv = vec ? n / 16 : 0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (size_t)gridDim.x * blockDim.x) {
+        const uint4 a = reinterpret_cast<const uint4*>(pred)[i];
+        const uint4 b = reinterpret_cast<const uint4*>(ref)[i];
+        const uint32_t P = nz_bits(a.x) | (nz_bits(a.y) << 4) | (nz_bits(a.z) << 8) | (nz_bits(a.w) << 12);
+        const uint32_t T = nz_bits(b.x) | (nz_bits(b.y) << 4) | (nz_bits(b.z) << 8) | (nz_bits(b.w) << 12);
+        tp += __popc(P & T);
+        fp += __popc(P & ~T);
+        fn += __popc(~P & T & 0xffffu);
+    }
+    for (size_t i = nv * 16 + (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x) {
         const bool p = pred[i] != 0, t = ref[i] != 0;
         tp += (p && t);
         fp += (p && !t);
         fn += (!p && t);
-        tn += (!p && !t);
     }
     for (int m = 32; m > 0; m >>= 1) {
         tp += __shfl_xor(tp, m, 64);
         fp += __shfl_xor(fp, m, 64);
         fn += __shfl_xor(fn, m, 64);
-        tn += __shfl_xor(tn, m, 64);
     }
+    const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        atomicAdd(&out[0], tp);
-        atomicAdd(&out[1], fp);
-        atomicAdd(&out[2], fn);
-        atomicAdd(&out[3], tn);
+        red[0][w] = tp;
+        red[1][w] = fp;
+        red[2][w] = fn;
     }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        unsigned long long t = 0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += red[threadIdx.x][k];
+        partial[(size_t)blockIdx.x * 3 + threadIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_confusion_sum(const unsigned long long* __restrict__ partial,
+                                                      int n_blocks, size_t n,
+                                                      unsigned long long* __restrict__ out) {
+    if (threadIdx.x < 3) {
+        unsigned long long t = 0;
+        for (int b = 0; b < n_blocks; ++b) t += partial[(size_t)b * 3 + threadIdx.x];
+        out[threadIdx.x] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) out[3] = n - out[0] - out[1] - out[2];
 }
 
 // ---------------------------------------------------------------------------
@@ -256,9 +288,10 @@ hipError_t launch_route(hipStream_t st, const float* logits, int n_views, int ti
 
 hipError_t launch_confusion(hipStream_t st, const uint8_t* pred, const uint8_t* ref, size_t n,
                             unsigned long long* dev4) {
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, dev4, 4);
-    hipLaunchKernelGGL(k_confusion, dim3(grid_for(n, 256 * 16, 4096)), dim3(256), 0, st, pred, ref,
-                       n, dev4);
+    // dev4: 4 results, then room for kConfusionBlocks * 3 partials
+    const int nb = grid_for(n, 256 * 16 * 4, kConfusionBlocks);
+    hipLaunchKernelGGL(k_confusion, dim3(nb), dim3(256), 0, st, pred, ref, n, dev4 + 4);
+    hipLaunchKernelGGL(k_confusion_sum, dim3(1), dim3(64), 0, st, dev4 + 4, nb, n, dev4);
     return hipGetLastError();
 }
 

@@ -567,7 +567,7 @@ extern "C" occl_status occl_confusion(occl_ctx* ctx, const uint8_t* pred, const 
     }
     (void)hipSetDevice(ctx->device);
     void* dev;
-    occl_status s = ctx->ensure("confusion", 4 * sizeof(unsigned long long), &dev);
+    occl_status s = ctx->ensure("confusion", (4 + 3 * (size_t)kConfusionBlocks) * sizeof(unsigned long long), &dev);
     if (s != OCCL_OK) return s;
     hipError_t e = launch_confusion(ctx->stream, pred, ref, (size_t)n, (unsigned long long*)dev);
     if (e != hipSuccess) return ctx->hip_fail(e, "confusion");

@@ -149,6 +149,9 @@ hipError_t launch_route(hipStream_t st, const float* logits, int n_views, int ti
                         float z_lo, float z_hi, const ViewTable& vt, const int* h, uint8_t* tstate,
                         uint8_t* tnear, int* stencil_ws);
 
+// TP, FP, FN, TN of two masks into dev[0..3]; dev holds 4 + 3 * kConfusionBlocks
+// entries (the rest is scratch for per-block partials).
+constexpr int kConfusionBlocks = 1024;
 hipError_t launch_confusion(hipStream_t st, const uint8_t* pred, const uint8_t* ref, size_t n,
                             unsigned long long* dev4);
 
