@@ -249,6 +249,35 @@ def profiles_from(run_dir: str, workload: str) -> int:
     return 0
 
 
+def bench_batched(ctx, steps: int, tune: bool):
+    """64 frames of mixed size (640x480 .. 2048x1536, c1 statistics, 8 views,
+    per-frame L) in one graph launch per step."""
+    import torch
+    from paper_2408_14050_amd import occl, scenes
+    frames = scenes.make_batch(seed=3000, n_frames=64)
+    Ds = [torch.from_numpy(f.D).cuda() for f in frames]
+    Ms = [torch.empty((f.n_views, f.H, f.W), dtype=torch.uint8, device="cuda") for f in frames]
+    batch = [(D, M, f.scan_len) for D, M, f in zip(Ds, Ms, frames)]
+    prm = occl.params(**frames[0].params)
+    shape = None
+    if tune:
+        shape = ctx.occl_autotune_batched(batch, frames[0].angles, frames[0].ratios, prm, reps=3)
+    for _ in range(3):
+        ctx.occl_detect_batched(batch, frames[0].angles, frames[0].ratios, prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.occl_detect_batched(batch, frames[0].angles, frames[0].ratios, prm)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    pv = sum(f.pixel_views for f in frames)
+    alg = sum((4 + f.n_views) * f.H * f.W for f in frames)
+    return {"workload": "c3: 64 frames from {640x480, 1280x960, 1920x1080, 2048x1536}, 8 views, "
+                        "seed 3000", "frames_per_s": round(64 / dt, 1),
+            "ms_per_launch": round(dt * 1e3, 4), "mpixel_views_per_s": round(pv / dt / 1e6, 1),
+            "alg_gbps": round(alg / dt / 1e9, 1), "launch_shape": shape}
+
+
 def cnn_flops(H: int, W: int) -> int:
     """Multiply-adds x 2 of the tile network's convolutions on one H x W view."""
     layers = [(8, 32, 2), (32, 32, 2), (32, 32, 2), (32, 32, 2), (32, 32, 1), (32, 1, 1)]
@@ -273,7 +302,7 @@ def bench_learned(ctx, steps: int, n_eval: int):
     for sc in frames:
         D = torch.from_numpy(sc.D).cuda()
         M = ctx.occl_detect(D, angles, ratios, occl.params(scan_len_per_view=sc.scan_len))
-        Z = ctx.occl_cnn_forward(ctx.occl_cnn_pack(D, angles, ratios, sc.scan_len))
+        Z = ctx.occl_cnn_propose(D, angles, ratios, sc.scan_len)
         st = torch.empty(Z.shape, dtype=torch.uint8, device="cuda")
         for b in bands:
             prm = occl.params(scan_len_per_view=sc.scan_len, cnn_lo=b[0], cnn_hi=b[1],

@@ -1,0 +1,47 @@
+"""Static checks of bench.py and __graft_entry__.py on the CPU: every name
+they call is defined, imported or a builtin (a missing helper would only
+show up on the GPU machine), and the multi-GPU request exits with its message."""
+import ast
+import builtins
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _undefined_calls(path):
+    tree = ast.parse(open(path).read())
+    known = set(dir(builtins))
+    for node in ast.walk(tree):
+        if isinstance(node, (ast.FunctionDef, ast.ClassDef)):
+            known.add(node.name)
+            known.update(a.arg for a in node.args.args + node.args.kwonlyargs) if isinstance(node, ast.FunctionDef) else None
+        elif isinstance(node, (ast.Import, ast.ImportFrom)):
+            known.update((a.asname or a.name).split(".")[0] for a in node.names)
+        elif isinstance(node, ast.Name) and isinstance(node.ctx, ast.Store):
+            known.add(node.id)
+        elif isinstance(node, ast.arg):
+            known.add(node.arg)
+        elif isinstance(node, (ast.comprehension,)):
+            for n in ast.walk(node.target):
+                if isinstance(n, ast.Name):
+                    known.add(n.id)
+    missing = set()
+    for node in ast.walk(tree):
+        if isinstance(node, ast.Call) and isinstance(node.func, ast.Name) and node.func.id not in known:
+            missing.add(node.func.id)
+    return missing
+
+
+@pytest.mark.parametrize("name", ["bench.py", "__graft_entry__.py"])
+def test_every_called_name_is_defined(name):
+    assert _undefined_calls(os.path.join(ROOT, name)) == set()
+
+
+def test_bench_refuses_several_gpus():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
