@@ -125,7 +125,7 @@ def cpu_baseline(sc, seconds: float):
 # profiling helpers (run under rocprofv3 on the GPU machine, summarised here)
 # ---------------------------------------------------------------------------
 PROFILE_CMD = ("rocprofv3 {mode} -d gpurun_out/{out} -o run -- python3 bench.py --steps 20 "
-               "--warmup 2 --no-cpu-baseline --no-context --no-check --no-learned")
+               "--warmup 2 --no-cpu-baseline --no-context --no-check --no-learned --no-quality")
 LEARNED_PROFILE_CMD = ("rocprofv3 {mode} -d gpurun_out/{out} -o run -- python3 bench.py --learned-only "
                        "--learned-steps 10 --learned-eval 1")
 BATCH_WORKLOAD = "c3 64 mixed frames seed 3000"
@@ -278,6 +278,46 @@ def bench_batched(ctx, steps: int, tune: bool):
             "alg_gbps": round(alg / dt / 1e9, 1), "launch_shape": shape}
 
 
+def bench_quality(ctx, n_frames: int = 4):
+    """Eq. (7) of the exact method against forward-warping ground truth
+    (occl_zbuffer) on c1 frames: configs' L and Eq. (3)'s L."""
+    import torch
+    from paper_2408_14050_amd import occl, scenes
+    out = {"workload": f"c1 1280x960 x8 views seeds 1000..{1000 + n_frames - 1}",
+           "reference": "forward-warping z-buffer (nearest target pixel, beta 0.5)"}
+    for name, mode in (("scan_len_config", 0), ("scan_len_eq3", -1)):
+        acc = [0, 0, 0, 0]
+        per_frame = []
+        for k in range(n_frames):
+            sc = scenes.make_scene("c1", 1000 + k)
+            D = torch.from_numpy(sc.D).cuda()
+            if mode == 0:
+                prm = occl.params(**sc.params, scan_len_per_view=sc.scan_len)
+            else:
+                prm = occl.params(**sc.params, scan_len=-1)
+            M = ctx.occl_detect(D, sc.angles, sc.ratios, prm)
+            Z = ctx.occl_zbuffer(D, sc.angles, sc.ratios, sc.params["disp_thr"])
+            q = ctx.occl_quality(M, Z)
+            per_frame.append(q["f1"])
+            for i, key in enumerate(("tp", "fp", "fn", "tn")):
+                acc[i] += q[key]
+        tp, fp, fn = acc[0], acc[1], acc[2]
+        P, R = tp / max(1, tp + fp), tp / max(1, tp + fn)
+        out[name] = {"precision": round(P, 4), "recall": round(R, 4), "f1": round(2 * P * R / (P + R), 4),
+                     "f1_per_frame_mean": round(sum(per_frame) / len(per_frame), 4),
+                     "iou": round(tp / max(1, tp + fp + fn), 4)}
+    sc = scenes.make_scene("c1", 1000)
+    D = torch.from_numpy(sc.D).cuda()
+    Z = ctx.occl_zbuffer(D, sc.angles, sc.ratios, 0.5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        ctx.occl_zbuffer(D, sc.angles, sc.ratios, 0.5, M=Z)
+    torch.cuda.synchronize()
+    out["zbuffer_ms"] = round((time.perf_counter() - t0) / 20 * 1e3, 4)
+    return out
+
+
 def cnn_flops(H: int, W: int) -> int:
     """Multiply-adds x 2 of the tile network's convolutions on one H x W view."""
     layers = [(8, 32, 2), (32, 32, 2), (32, 32, 2), (32, 32, 2), (32, 32, 1), (32, 1, 1)]
@@ -374,6 +414,7 @@ def main() -> int:
     ap.add_argument("--profiles-from", default=None, metavar="DIR")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-only", action="store_true", help="only the learned-path section")
+    ap.add_argument("--no-quality", action="store_true")
     ap.add_argument("--learned-steps", type=int, default=50)
     ap.add_argument("--learned-eval", type=int, default=4, help="c4 frames for IoU / P / R")
     args = ap.parse_args()
@@ -497,6 +538,9 @@ def main() -> int:
 
     if not args.no_learned:
         out["learned"] = bench_learned(ctx, args.learned_steps, args.learned_eval)
+
+    if not args.no_quality:
+        out["quality_vs_zbuffer"] = bench_quality(ctx)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)

@@ -260,6 +260,19 @@ occl_status occl_detect_routed(occl_ctx* ctx, const float* D, int32_t H, int32_t
                                const occl_params* params, const float* logits, uint8_t* M,
                                uint8_t* tile_state);
 
+/* Ground truth for the quality counts of Eq. (7), by forward warping (a
+ * z-buffer).  Under the reading that a centre pixel p lands at p - r*D(p)*u
+ * in the view of direction u = (cos alpha, sin alpha), take the nearest target
+ * pixel (t = r*D(p), tx = rint(x - t*cos alpha), ty = rint(y - t*sin alpha),
+ * fp32, half to even).  M[v][y][x] = 1 iff some pixel (p itself included)
+ * lands on the same target with a disparity larger by more than beta.
+ * Targets outside the peripheral frame count as well.
+ *   D  device fp32 [H][W], finite (non-finite values: OCCL_ERR_INVALID_ARG)
+ *   M  device uint8 [n_views][H][W]
+ * Reads min/max of D back to size its target grid, so it synchronises. */
+occl_status occl_zbuffer(occl_ctx* ctx, const float* D, int32_t H, int32_t W, int32_t n_views,
+                         const double* angles_deg, const float* ratios, float beta, uint8_t* M);
+
 /* Waits for the context's stream; reports a pending device error. */
 occl_status occl_sync(occl_ctx* ctx);
 

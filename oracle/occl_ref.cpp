@@ -458,4 +458,51 @@ int occl_ref_confusion(const unsigned char* pred, const unsigned char* ref, long
     return 0;
 }
 
+/* Ground truth by forward warping (z-buffer): the reference the quality
+ * counts of Eq. (7) are taken against.  Under R1 a centre pixel p = (x, y)
+ * with disparity D(p) lands at p - r*D(p)*u in the peripheral view of
+ * direction u = (c, s); the target pixel is the nearest one:
+ *     t = r*D(p) (fp32),  tx = rint(x - t*c),  ty = rint(y - t*s)
+ * (fp32, round half to even).  p is occluded in that view iff some pixel q
+ * (p itself included) lands on the same target pixel with D(q) - D(p) > beta
+ * (fp32 subtraction).  The target may lie outside the peripheral frame: two
+ * centre pixels landing on the same outside position still occlude each other.
+ * M: [n_views][H][W] bytes 0 / 1. */
+int occl_ref_zbuffer(const float* D, int H, int W, int n_views, const double* angles,
+                     const float* ratios, float beta, unsigned char* M) {
+    if (!D || !M || H < 1 || W < 1 || n_views < 1 || !angles || !ratios) return -1;
+    const size_t HW = (size_t)H * W;
+    for (int v = 0; v < n_views; ++v) {
+        float c, s;
+        if (occl_ref_direction(angles[v], &c, &s) != 0) return -1;
+        const float r = ratios[v];
+        std::vector<long long> key(HW);
+        for (int y = 0; y < H; ++y)
+            for (int x = 0; x < W; ++x) {
+                const float t = r * D[(size_t)y * W + x];
+                const long long tx = (long long)std::nearbyint((float)x - t * c);
+                const long long ty = (long long)std::nearbyint((float)y - t * s);
+                key[(size_t)y * W + x] = (ty << 32) ^ (tx & 0xffffffffLL);
+            }
+        // largest disparity landing on each target: pixel indices sorted by
+        // target key, then the maximum of each run of equal keys
+        std::vector<size_t> order(HW);
+        for (size_t i = 0; i < HW; ++i) order[i] = i;
+        std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return key[a] < key[b]; });
+        std::vector<float> best(HW);
+        for (size_t i = 0; i < HW;) {
+            size_t j = i;
+            float m = D[order[i]];
+            while (j < HW && key[order[j]] == key[order[i]]) {
+                m = std::max(m, D[order[j]]);
+                ++j;
+            }
+            for (size_t k = i; k < j; ++k) best[order[k]] = m;
+            i = j;
+        }
+        for (size_t i = 0; i < HW; ++i) M[(size_t)v * HW + i] = (best[i] - D[i] > beta) ? 1 : 0;
+    }
+    return 0;
+}
+
 }  // extern "C"

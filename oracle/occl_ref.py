@@ -37,6 +37,7 @@ def lib():
         L.occl_ref_detect.argtypes = [fp, C.c_int, C.c_int, C.c_int, dp, fp, i32, C.c_float,
                                       C.c_float, C.c_float, C.c_int, u8, u8, i64]
         L.occl_ref_confusion.argtypes = [u8, u8, C.c_longlong, i64]
+        L.occl_ref_zbuffer.argtypes = [fp, C.c_int, C.c_int, C.c_int, dp, fp, C.c_float, u8]
         L.occl_ref_scanline_pixels.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
                                                C.c_int, i32, i32, C.c_int]
         L.occl_ref_detect_window.argtypes = [fp, C.c_int, C.c_int, C.c_int, dp, fp, i32, C.c_float,
@@ -180,3 +181,28 @@ def confusion(pred, ref):
                                   _p(out, C.c_longlong))
     assert rc == 0
     return {"tp": int(out[0]), "fp": int(out[1]), "fn": int(out[2]), "tn": int(out[3])}
+
+
+def zbuffer(D, angles, ratios, beta=0.5):
+    """Forward-warping ground truth occlusion masks [V, H, W] (occl_ref_zbuffer)."""
+    D = _f32(D)
+    H, W = D.shape
+    a = np.ascontiguousarray(np.atleast_1d(angles), dtype=np.float64)
+    r = _f32(np.atleast_1d(ratios))
+    M = np.empty((a.shape[0], H, W), np.uint8)
+    rc = lib().occl_ref_zbuffer(_p(D, C.c_float), H, W, a.shape[0], _p(a, C.c_double),
+                                _p(r, C.c_float), float(beta), _p(M, C.c_ubyte))
+    if rc != 0:
+        raise ValueError("invalid argument to occl_ref_zbuffer")
+    return M
+
+
+def quality(pred, ref):
+    """Eq. (7): precision, recall, F1 and IoU of a predicted mask against a
+    reference mask (pooled counts)."""
+    c = confusion(pred, ref)
+    tp, fp, fn = c["tp"], c["fp"], c["fn"]
+    P = tp / (tp + fp) if tp + fp else 1.0
+    R = tp / (tp + fn) if tp + fn else 1.0
+    F = 2 * P * R / (P + R) if P + R else 0.0
+    return {"precision": P, "recall": R, "f1": F, "iou": tp / (tp + fp + fn) if tp + fp + fn else 1.0, **c}

@@ -1,6 +1,8 @@
 // k_util.hip -- small helper kernels: statistics of D (automatic scan length,
 // input validation), the edge magnitude / angle maps of Eq. (1) as outputs,
 // and the confusion counts behind Eq. (7).
+#include <cmath>
+
 #include "occl_internal.h"
 
 namespace occl {
@@ -232,6 +234,72 @@ __global__ __launch_bounds__(256) void k_route_near(const uint8_t* __restrict__ 
     }
 }
 
+// ---------------------------------------------------------------------------
+// forward-warping ground truth (z-buffer) for the quality counts of Eq. (7)
+// ---------------------------------------------------------------------------
+// Pixel p = (x, y) lands at the nearest pixel of p - r*D(p)*u: t = r*D(p),
+// tx = rint(x - t*c), ty = rint(y - t*s) (fp32, half to even).  Per view the
+// targets live in a grid padded by `pad` pixels on every side (pad exceeds
+// r * max|D|, so every target fits); the grid holds the largest disparity
+// per target as an order-preserving uint32 (0 = nothing landed).
+struct ZViews {
+    float c[OCCL_MAX_VIEWS], s[OCCL_MAX_VIEWS], r[OCCL_MAX_VIEWS];
+    int pad[OCCL_MAX_VIEWS];
+    long long off[OCCL_MAX_VIEWS + 1];  // first grid cell of view v
+};
+
+__device__ __forceinline__ long long ztarget(const ZViews& zv, int v, int x, int y, float d, int H,
+                                             int W) {
+    const float t = __fmul_rn(zv.r[v], d);
+    const int tx = (int)rintf(__fsub_rn((float)x, __fmul_rn(t, zv.c[v])));
+    const int ty = (int)rintf(__fsub_rn((float)y, __fmul_rn(t, zv.s[v])));
+    const int p = zv.pad[v];
+    const int gw = W + 2 * p, gh = H + 2 * p;
+    const int gx = tx + p, gy = ty + p;
+    if (gx < 0 || gx >= gw || gy < 0 || gy >= gh) return -1;  // cannot happen for a finite D
+    return zv.off[v] + (long long)gy * gw + gx;
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_zbuf_splat(const float* __restrict__ D, int H, int W, int n_views,
+                                                    ZViews zv, uint32_t* __restrict__ best) {
+    const long long HW = (long long)H * W;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < HW * n_views;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int v = (int)(i / HW);
+        const long long k = i % HW;
+        const int y = (int)(k / W), x = (int)(k % W);
+        const float d = D[k];
+        const long long g = ztarget(zv, v, x, y, d, H, W);
+        if (g >= 0) atomicMax(&best[g], ford(d));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_zbuf_mark(const float* __restrict__ D, int H, int W, int n_views,
+                                                   ZViews zv, float beta, const uint32_t* __restrict__ best,
+                                                   uint8_t* __restrict__ M) {
+    const long long HW = (long long)H * W;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < HW * n_views;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int v = (int)(i / HW);
+        const long long k = i % HW;
+        const int y = (int)(k / W), x = (int)(k % W);
+        const float d = D[k];
+        const long long g = ztarget(zv, v, x, y, d, H, W);
+        uint8_t m = 0;
+        if (g >= 0) {
+            const uint32_t o = best[g];
+            const float b = __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
+            m = __fsub_rn(b, d) > beta ? 1 : 0;
+        }
+        M[i] = m;
+    }
+}
+
 inline int grid_for(size_t n, int per_block, int cap) {
     size_t g = (n + per_block - 1) / per_block;
     if (g < 1) g = 1;
@@ -283,6 +351,36 @@ hipError_t launch_route(hipStream_t st, const float* logits, int n_views, int ti
     hipLaunchKernelGGL(k_route_stencil, dim3(n_views), dim3(256), 0, st, rv, slack, cap, count, sten);
     hipLaunchKernelGGL(k_route_near, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, tstate, n_views,
                        tiles_y, tiles_x, cap, count, sten, tnear);
+    return hipGetLastError();
+}
+
+long long zbuffer_cells(int H, int W, int n_views, const float* ratios, float max_abs_d) {
+    long long n = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const int pad = (int)std::ceil((double)ratios[v] * (double)max_abs_d) + 2;
+        n += (long long)(H + 2 * pad) * (W + 2 * pad);
+    }
+    return n;
+}
+
+hipError_t launch_zbuffer(hipStream_t st, const float* D, int H, int W, int n_views, const ViewTable& vt,
+                          float max_abs_d, float beta, uint32_t* best, uint8_t* M) {
+    ZViews zv{};
+    long long off = 0;
+    for (int v = 0; v < n_views; ++v) {
+        zv.c[v] = vt.c[v];
+        zv.s[v] = vt.s[v];
+        zv.r[v] = vt.r[v];
+        zv.pad[v] = (int)std::ceil((double)vt.r[v] * (double)max_abs_d) + 2;
+        zv.off[v] = off;
+        off += (long long)(H + 2 * zv.pad[v]) * (W + 2 * zv.pad[v]);
+    }
+    zv.off[n_views] = off;
+    const size_t n = (size_t)H * W * n_views;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for((size_t)off, 256, 8192)), dim3(256), 0, st, best, off);
+    hipLaunchKernelGGL(k_zbuf_splat, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, D, H, W, n_views, zv, best);
+    hipLaunchKernelGGL(k_zbuf_mark, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, D, H, W, n_views, zv, beta,
+                       best, M);
     return hipGetLastError();
 }
 

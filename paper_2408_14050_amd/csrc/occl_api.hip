@@ -557,6 +557,39 @@ extern "C" occl_status occl_edges(occl_ctx* ctx, const float* D, int32_t H, int3
     return OCCL_OK;
 }
 
+extern "C" occl_status occl_zbuffer(occl_ctx* ctx, const float* D, int32_t H, int32_t W, int32_t n_views,
+                                    const double* angles_deg, const float* ratios, float beta,
+                                    uint8_t* M) {
+    if (!ctx) return OCCL_ERR_INVALID_ARG;
+    if (H < 0 || W < 0 || n_views < 0 || n_views > OCCL_MAX_VIEWS || !std::isfinite(beta))
+        return ctx->fail(OCCL_ERR_INVALID_ARG, "zbuffer arguments");
+    if ((size_t)H * W == 0 || n_views == 0) return OCCL_OK;
+    if (!D || !M || !angles_deg || !ratios) return ctx->fail(OCCL_ERR_INVALID_ARG, "NULL argument");
+    if ((size_t)H * W > (size_t)1 << 31) return ctx->fail(OCCL_ERR_UNSUPPORTED, "frame too large");
+    ViewTable vt{};
+    for (int v = 0; v < n_views; ++v) {
+        if (!std::isfinite(angles_deg[v]) || !std::isfinite(ratios[v]) || !(ratios[v] > 0.0f))
+            return ctx->fail(OCCL_ERR_INVALID_ARG, "view");
+        direction_of(angles_deg[v], &vt.c[v], &vt.s[v]);
+        vt.r[v] = ratios[v];
+    }
+    (void)hipSetDevice(ctx->device);
+    float mn, mx;
+    uint32_t bad;
+    occl_status s = ctx->d_stats(D, (size_t)H * W, &mn, &mx, &bad);
+    if (s != OCCL_OK) return s;
+    if (bad) return ctx->fail(OCCL_ERR_INVALID_ARG, "D holds non-finite values");
+    const float amax = std::max(std::fabs(mn), std::fabs(mx));
+    const long long cells = zbuffer_cells(H, W, n_views, ratios, amax);
+    if (cells > (1ll << 32)) return ctx->fail(OCCL_ERR_UNSUPPORTED, "disparities too large for the target grid");
+    void* best;
+    s = ctx->ensure("zbuffer", (size_t)cells * sizeof(uint32_t), &best);
+    if (s != OCCL_OK) return s;
+    hipError_t e = launch_zbuffer(ctx->stream, D, H, W, n_views, vt, amax, beta, (uint32_t*)best, M);
+    if (e != hipSuccess) return ctx->hip_fail(e, "zbuffer");
+    return OCCL_OK;
+}
+
 extern "C" occl_status occl_confusion(occl_ctx* ctx, const uint8_t* pred, const uint8_t* ref,
                                       int64_t n, uint64_t* out) {
     if (!ctx || !out || n < 0) return OCCL_ERR_INVALID_ARG;

@@ -149,6 +149,13 @@ hipError_t launch_route(hipStream_t st, const float* logits, int n_views, int ti
                         float z_lo, float z_hi, const ViewTable& vt, const int* h, uint8_t* tstate,
                         uint8_t* tnear, int* stencil_ws);
 
+// Forward-warping ground truth: M[v][y][x] = 1 iff some pixel lands on the
+// same nearest target pixel of view v with a disparity larger by more than
+// beta.  best: workspace of zbuffer_cells(...) uint32; max_abs_d >= max |D|.
+long long zbuffer_cells(int H, int W, int n_views, const float* ratios, float max_abs_d);
+hipError_t launch_zbuffer(hipStream_t st, const float* D, int H, int W, int n_views, const ViewTable& vt,
+                          float max_abs_d, float beta, uint32_t* best, uint8_t* M);
+
 // TP, FP, FN, TN of two masks into dev[0..3]; dev holds 4 + 3 * kConfusionBlocks
 // entries (the rest is scratch for per-block partials).
 constexpr int kConfusionBlocks = 1024;

@@ -77,6 +77,8 @@ _SIGS = {
     "occl_edges": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
     "occl_confusion": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                  C.POINTER(C.c_uint64)]),
+    "occl_zbuffer": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                               C.POINTER(C.c_double), C.POINTER(C.c_float), C.c_float, C.c_void_p]),
     "occl_sync": (C.c_int, [C.c_void_p]),
     "occl_release": (C.c_int, [C.c_void_p]),
     "occl_status_string": (C.c_char_p, [C.c_int]),
@@ -281,6 +283,28 @@ class Context:
                                   out.ctypes.data_as(C.POINTER(C.c_uint64)))
         self._check(st, "occl_confusion")
         return {"tp": int(out[0]), "fp": int(out[1]), "fn": int(out[2]), "tn": int(out[3])}
+
+    def occl_zbuffer(self, D, angles, ratios, beta: float = 0.5, M=None):
+        """Forward-warping ground truth masks uint8 [V, H, W] (Eq. (7) reference)."""
+        torch = self._torch
+        a, r = self._views(angles, ratios)
+        H, W = int(D.shape[0]), int(D.shape[1])
+        if M is None:
+            M = torch.empty((a.shape[0], H, W), dtype=torch.uint8, device=D.device)
+        st = lib().occl_zbuffer(self.h, _ptr(D), H, W, int(a.shape[0]),
+                                a.ctypes.data_as(C.POINTER(C.c_double)),
+                                r.ctypes.data_as(C.POINTER(C.c_float)), float(beta), _ptr(M))
+        self._check(st, "occl_zbuffer")
+        return M
+
+    def occl_quality(self, pred, ref):
+        """Eq. (7) on the GPU counts: precision, recall, F1, IoU (pooled)."""
+        c = self.occl_confusion(pred, ref)
+        tp, fp, fn = c["tp"], c["fp"], c["fn"]
+        P = tp / (tp + fp) if tp + fp else 1.0
+        R = tp / (tp + fn) if tp + fn else 1.0
+        return {"precision": P, "recall": R, "f1": 2 * P * R / (P + R) if P + R else 0.0,
+                "iou": tp / (tp + fp + fn) if tp + fp + fn else 1.0, **c}
 
     def occl_profile_enable(self, enable: bool = True):
         self._check(lib().occl_profile_enable(self.h, int(bool(enable))), "occl_profile_enable")

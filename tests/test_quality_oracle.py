@@ -1,0 +1,114 @@
+"""Pins of the forward-warping ground truth (oracle occl_ref_zbuffer) and of
+the Eq. (7) quality harness, on the CPU."""
+import numpy as np
+import pytest
+
+from paper_2408_14050_amd import scenes
+from tests.test_oracle_pins import _layered_integer_scene, zbuffer_occlusion
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_zbuffer_matches_integer_brute_force(ref, seed):
+    """Integer disparities, axis directions, r = 1: every pixel lands exactly on
+    a pixel, so the nearest-pixel splat is the brute-force z-buffer."""
+    rng = np.random.default_rng(500 + seed)
+    H, W = int(rng.integers(8, 40)), int(rng.integers(8, 48))
+    D = _layered_integer_scene(rng, H, W, int(rng.integers(1, 6)))
+    beta = float(rng.choice([0.25, 0.5, 0.75]))
+    Z = ref.zbuffer(D, [0, 90, 180, 270], [1.0] * 4, beta)
+    for v, a in enumerate((0, 90, 180, 270)):
+        np.testing.assert_array_equal(Z[v], zbuffer_occlusion(D, a, beta), err_msg=f"alpha={a}")
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_zbuffer_equals_method_on_equality_class(ref, seed):
+    """On the z-buffer equality class the method's mask (Eqs. (1)-(6)) and the
+    ground truth coincide, so Eq. (7) gives P = R = F1 = 1."""
+    rng = np.random.default_rng(700 + seed)
+    H, W = int(rng.integers(10, 40)), int(rng.integers(10, 48))
+    D = _layered_integer_scene(rng, H, W, int(rng.integers(1, 5)))
+    L = int(2 * (D.max() - D.min()) + 4)
+    for a in (0, 90, 180, 270):
+        M, _, _ = ref.detect(D, [a], [1.0], [L], disp_thr=0.5)
+        Z = ref.zbuffer(D, [a], [1.0], 0.5)
+        q = ref.quality(M, Z)
+        assert q["precision"] == 1.0 and q["recall"] == 1.0 and q["f1"] == 1.0
+
+
+@pytest.mark.parametrize("dd", [1, 3, 7])
+@pytest.mark.parametrize("alpha", [0, 90, 180, 270])
+def test_zbuffer_closed_form_strip(ref, dd, alpha):
+    """Fronto-parallel rectangle of disparity d_b + dd on d_b: the occluded
+    pixels are exactly a strip dd wide on the side the rectangle moves over,
+    the full length of that edge (integer disparities, r = 1)."""
+    H, W, db = 40, 50, 2
+    D = np.full((H, W), db, np.float32)
+    y0, y1, x0, x1 = 12, 25, 15, 30
+    D[y0:y1, x0:x1] = db + dd
+    Z = ref.zbuffer(D, [alpha], [1.0], 0.5)[0]
+    E = np.zeros((H, W), np.uint8)
+    # the rectangle lands dd pixels further along -u than the background
+    if alpha == 0:
+        E[y0:y1, x0 - dd:x0] = 1
+    elif alpha == 180:
+        E[y0:y1, x1:x1 + dd] = 1
+    elif alpha == 90:
+        E[y0 - dd:y0, x0:x1] = 1
+    else:
+        E[y1:y1 + dd, x0:x1] = 1
+    np.testing.assert_array_equal(Z, E)
+
+
+def test_zbuffer_constant_and_monotone(ref):
+    D = np.full((20, 30), 3.7, np.float32)
+    assert ref.zbuffer(D, [0, 45, 200], [1.0, 1.4142135, 2.0], 0.5).sum() == 0
+    sc = scenes.make_c1_like(11, W=160, H=120, n_objects=6)
+    prev = None
+    for beta in (2.0, 1.0, 0.5, 0.1):  # decreasing beta can only add pixels
+        Z = ref.zbuffer(sc.D, sc.angles, sc.ratios, beta)
+        if prev is not None:
+            assert np.all(Z >= prev)
+        prev = Z
+    assert prev.sum() > 0
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_zbuffer_transpose_symmetry(ref, seed):
+    """Z(D^T, 90 - alpha) = Z(D, alpha)^T exactly: transposition swaps x and y
+    and the direction vector's components (octant-exact rule)."""
+    sc = scenes.make_c1_like(20 + seed, W=96, H=72, n_objects=6)
+    angles = [0, 30, 45, 90, 135, 210, 333]
+    ratios = np.array([1.0, 1.3, 1.4142135, 1.0, 0.7, 2.0, 1.1], np.float32)
+    Z = ref.zbuffer(sc.D, angles, ratios, 0.5)
+    Zt = ref.zbuffer(np.ascontiguousarray(sc.D.T), [90 - a for a in angles], ratios, 0.5)
+    for v in range(len(angles)):
+        np.testing.assert_array_equal(Zt[v], Z[v].T)
+
+
+def test_quality_counts_and_definitions(ref):
+    pred = np.array([1, 1, 0, 0, 1, 0], np.uint8)
+    gt = np.array([1, 0, 1, 0, 1, 0], np.uint8)
+    q = ref.quality(pred, gt)
+    assert (q["tp"], q["fp"], q["fn"], q["tn"]) == (2, 1, 1, 2)
+    assert q["precision"] == 2 / 3 and q["recall"] == 2 / 3
+    assert abs(q["f1"] - 2 / 3) < 1e-15 and q["iou"] == 0.5
+
+
+def test_method_against_ground_truth_on_c1_statistics(ref):
+    """The method against forward-warping ground truth on a c1-statistics
+    scene (Eq. (7) counts).  With Eq. (3)'s scan length (2 r (max D - min D))
+    every strip lies within the scanline's reach and recall is near 1; the
+    misses are the fractional-disparity pixels where the nearest-pixel splat
+    and the |dW| < zeta adjacency test round differently, which also gives the
+    ~8 % of extra pixels (precision).  With the configs' shorter
+    L = ceil(max(D) r) + 2 the reach h = L/2 is below the widest strips
+    (r dD up to 48 r), so those strips are cut at h and recall drops: a
+    property of that L, kept as an expected shortfall."""
+    sc = scenes.make_c1_like(1000, W=320, H=240, n_objects=10)
+    Z = ref.zbuffer(sc.D, sc.angles, sc.ratios, sc.params["disp_thr"])
+    M3, _, _ = ref.detect(sc.D, sc.angles, sc.ratios, ref.scan_len(sc.D, sc.ratios, 1))
+    q3 = ref.quality(M3, Z)
+    assert q3["recall"] > 0.97 and q3["precision"] > 0.85, q3
+    Mc, _, _ = ref.detect_scene(sc)
+    qc = ref.quality(Mc, Z)
+    assert qc["recall"] < 0.8 and qc["precision"] > 0.85, qc
