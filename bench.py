@@ -318,6 +318,27 @@ def bench_quality(ctx, n_frames: int = 4):
     return out
 
 
+def bench_fusion(ctx, steps: int = 50):
+    """Median fusion of 8 noisy per-view maps into D at 1280x960 (HBM-bound:
+    (K + 1) * 4 bytes per pixel)."""
+    import torch
+    from paper_2408_14050_amd import scenes
+    sc = scenes.make_scene("c1", 1002)
+    K = 8
+    maps = torch.from_numpy(scenes.fusion_maps(1, sc.D, K=K)).cuda()
+    D = ctx.occl_median_fuse(maps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.occl_median_fuse(maps, D=D)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    alg = (K + 1) * 4 * sc.H * sc.W
+    return {"workload": f"8 maps 1280x960 (c1 seed 1002 + noise 0.3, 5 % outliers, 3 % holes)",
+            "ms": round(dt * 1e3, 4), "alg_bytes": alg, "alg_gbps": round(alg / dt / 1e9, 1),
+            "hbm_frac": round(alg / dt / 1e9 / HBM_PEAK_GBPS, 4)}
+
+
 def cnn_flops(H: int, W: int) -> int:
     """Multiply-adds x 2 of the tile network's convolutions on one H x W view."""
     layers = [(8, 32, 2), (32, 32, 2), (32, 32, 2), (32, 32, 2), (32, 32, 1), (32, 1, 1)]
@@ -541,6 +562,7 @@ def main() -> int:
 
     if not args.no_quality:
         out["quality_vs_zbuffer"] = bench_quality(ctx)
+        out["median_fusion"] = bench_fusion(ctx)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)

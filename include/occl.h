@@ -260,6 +260,15 @@ occl_status occl_detect_routed(occl_ctx* ctx, const float* D, int32_t H, int32_t
                                const occl_params* params, const float* logits, uint8_t* M,
                                uint8_t* tile_state);
 
+/* The step before the detector: the fused centre disparity D as the
+ * pixel-wise median of K per-view disparity maps (Sec. 4 fuses the views'
+ * maps by their median).  maps: device fp32 [K][H][W], NaN = no value at that
+ * pixel; D: device fp32 [H][W] = median of the non-NaN values (an even count
+ * averages the two middle ones, (a + b) * 0.5 in fp32), NaN where all are NaN.
+ * K = 1..16 (more: OCCL_ERR_UNSUPPORTED). */
+occl_status occl_median_fuse(occl_ctx* ctx, const float* maps, int32_t K, int32_t H, int32_t W,
+                             float* D);
+
 /* Ground truth for the quality counts of Eq. (7), by forward warping (a
  * z-buffer).  Under the reading that a centre pixel p lands at p - r*D(p)*u
  * in the view of direction u = (cos alpha, sin alpha), take the nearest target

@@ -505,4 +505,29 @@ int occl_ref_zbuffer(const float* D, int H, int W, int n_views, const double* an
     return 0;
 }
 
+/* Pixel-wise median fusion of K per-view disparity maps into the centre
+ * map D (the step before the method, Sec. 4's multispectral pipeline):
+ * D[i] = median of the non-NaN values maps[k][i], k = 0..K-1; for an even
+ * count the mean of the two middle values, (a + b) * 0.5 in fp32; NaN if
+ * every value is NaN.  maps: [K][H*W]. */
+int occl_ref_median_fuse(const float* maps, int K, long long n, float* D) {
+    if (!maps || !D || K < 1 || K > 64 || n < 0) return -1;
+    std::vector<float> v;
+    for (long long i = 0; i < n; ++i) {
+        v.clear();
+        for (int k = 0; k < K; ++k) {
+            const float x = maps[(size_t)k * n + i];
+            if (!std::isnan(x)) v.push_back(x);
+        }
+        if (v.empty()) {
+            D[i] = std::nanf("");
+            continue;
+        }
+        std::sort(v.begin(), v.end());
+        const size_t m = v.size();
+        D[i] = (m % 2) ? v[m / 2] : (v[m / 2 - 1] + v[m / 2]) * 0.5f;
+    }
+    return 0;
+}
+
 }  // extern "C"

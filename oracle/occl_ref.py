@@ -38,6 +38,7 @@ def lib():
                                       C.c_float, C.c_float, C.c_int, u8, u8, i64]
         L.occl_ref_confusion.argtypes = [u8, u8, C.c_longlong, i64]
         L.occl_ref_zbuffer.argtypes = [fp, C.c_int, C.c_int, C.c_int, dp, fp, C.c_float, u8]
+        L.occl_ref_median_fuse.argtypes = [fp, C.c_int, C.c_longlong, fp]
         L.occl_ref_scanline_pixels.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
                                                C.c_int, i32, i32, C.c_int]
         L.occl_ref_detect_window.argtypes = [fp, C.c_int, C.c_int, C.c_int, dp, fp, i32, C.c_float,
@@ -206,3 +207,14 @@ def quality(pred, ref):
     R = tp / (tp + fn) if tp + fn else 1.0
     F = 2 * P * R / (P + R) if P + R else 0.0
     return {"precision": P, "recall": R, "f1": F, "iou": tp / (tp + fp + fn) if tp + fp + fn else 1.0, **c}
+
+
+def median_fuse(maps):
+    """Pixel-wise NaN-ignoring median of K maps [K, H, W] (occl_ref_median_fuse)."""
+    maps = _f32(maps)
+    K = maps.shape[0]
+    out = np.empty(maps.shape[1:], np.float32)
+    rc = lib().occl_ref_median_fuse(_p(maps, C.c_float), K, int(out.size), _p(out, C.c_float))
+    if rc != 0:
+        raise ValueError("invalid argument to occl_ref_median_fuse")
+    return out

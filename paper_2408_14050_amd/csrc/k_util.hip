@@ -300,6 +300,45 @@ __global__ __launch_bounds__(256) void k_zbuf_mark(const float* __restrict__ D, 
     }
 }
 
+// ---------------------------------------------------------------------------
+// pixel-wise median fusion of K per-view disparity maps (NaN = no value)
+// ---------------------------------------------------------------------------
+// Per pixel the K values sit in registers; NaN becomes +inf and is not
+// counted; an odd-even transposition network (K rounds) sorts them; the
+// median of the first m = count(non-NaN) is picked with compile-time selects
+// (an even m averages the two middle values: (a + b) * 0.5).
+template <int K>
+__global__ __launch_bounds__(256) void k_median_fuse(const float* __restrict__ maps, long long n,
+                                                     float* __restrict__ D) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        float v[K];
+        int m = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const float x = maps[(size_t)k * n + i];
+            const bool ok = !isnan(x);
+            v[k] = ok ? x : INFINITY;
+            m += ok ? 1 : 0;
+        }
+#pragma unroll
+        for (int round = 0; round < K; ++round)
+#pragma unroll
+            for (int k = round & 1; k + 1 < K; k += 2) {
+                const float a = v[k], b = v[k + 1];
+                v[k] = fminf(a, b);
+                v[k + 1] = fmaxf(a, b);
+            }
+        float lo = 0.0f, hi = 0.0f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            lo = (k == (m - 1) / 2) ? v[k] : lo;
+            hi = (k == m / 2) ? v[k] : hi;
+        }
+        D[i] = m == 0 ? __int_as_float(0x7fc00000) : ((m & 1) ? hi : __fmul_rn(__fadd_rn(lo, hi), 0.5f));
+    }
+}
+
 inline int grid_for(size_t n, int per_block, int cap) {
     size_t g = (n + per_block - 1) / per_block;
     if (g < 1) g = 1;
@@ -381,6 +420,21 @@ hipError_t launch_zbuffer(hipStream_t st, const float* D, int H, int W, int n_vi
     hipLaunchKernelGGL(k_zbuf_splat, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, D, H, W, n_views, zv, best);
     hipLaunchKernelGGL(k_zbuf_mark, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, D, H, W, n_views, zv, beta,
                        best, M);
+    return hipGetLastError();
+}
+
+hipError_t launch_median_fuse(hipStream_t st, const float* maps, int K, long long n, float* D) {
+    const dim3 grid(grid_for((size_t)n, 256, 8192)), block(256);
+    switch (K) {
+#define OCCL_MEDIAN_CASE(k) \
+    case k: hipLaunchKernelGGL(k_median_fuse<k>, grid, block, 0, st, maps, n, D); break;
+        OCCL_MEDIAN_CASE(1) OCCL_MEDIAN_CASE(2) OCCL_MEDIAN_CASE(3) OCCL_MEDIAN_CASE(4)
+        OCCL_MEDIAN_CASE(5) OCCL_MEDIAN_CASE(6) OCCL_MEDIAN_CASE(7) OCCL_MEDIAN_CASE(8)
+        OCCL_MEDIAN_CASE(9) OCCL_MEDIAN_CASE(10) OCCL_MEDIAN_CASE(11) OCCL_MEDIAN_CASE(12)
+        OCCL_MEDIAN_CASE(13) OCCL_MEDIAN_CASE(14) OCCL_MEDIAN_CASE(15) OCCL_MEDIAN_CASE(16)
+#undef OCCL_MEDIAN_CASE
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

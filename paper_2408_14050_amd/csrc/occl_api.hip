@@ -590,6 +590,19 @@ extern "C" occl_status occl_zbuffer(occl_ctx* ctx, const float* D, int32_t H, in
     return OCCL_OK;
 }
 
+extern "C" occl_status occl_median_fuse(occl_ctx* ctx, const float* maps, int32_t K, int32_t H,
+                                        int32_t W, float* D) {
+    if (!ctx) return OCCL_ERR_INVALID_ARG;
+    if (H < 0 || W < 0 || K < 1) return ctx->fail(OCCL_ERR_INVALID_ARG, "median arguments");
+    if (K > 16) return ctx->fail(OCCL_ERR_UNSUPPORTED, "more than 16 maps");
+    if ((size_t)H * W == 0) return OCCL_OK;
+    if (!maps || !D) return ctx->fail(OCCL_ERR_INVALID_ARG, "NULL argument");
+    (void)hipSetDevice(ctx->device);
+    hipError_t e = launch_median_fuse(ctx->stream, maps, K, (long long)H * W, D);
+    if (e != hipSuccess) return ctx->hip_fail(e, "median_fuse");
+    return OCCL_OK;
+}
+
 extern "C" occl_status occl_confusion(occl_ctx* ctx, const uint8_t* pred, const uint8_t* ref,
                                       int64_t n, uint64_t* out) {
     if (!ctx || !out || n < 0) return OCCL_ERR_INVALID_ARG;

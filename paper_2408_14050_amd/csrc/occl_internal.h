@@ -156,6 +156,9 @@ long long zbuffer_cells(int H, int W, int n_views, const float* ratios, float ma
 hipError_t launch_zbuffer(hipStream_t st, const float* D, int H, int W, int n_views, const ViewTable& vt,
                           float max_abs_d, float beta, uint32_t* best, uint8_t* M);
 
+// D[i] = NaN-ignoring median of maps[k][i], k < K (1..16).
+hipError_t launch_median_fuse(hipStream_t st, const float* maps, int K, long long n, float* D);
+
 // TP, FP, FN, TN of two masks into dev[0..3]; dev holds 4 + 3 * kConfusionBlocks
 // entries (the rest is scratch for per-block partials).
 constexpr int kConfusionBlocks = 1024;

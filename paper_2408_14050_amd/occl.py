@@ -79,6 +79,7 @@ _SIGS = {
                                  C.POINTER(C.c_uint64)]),
     "occl_zbuffer": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
                                C.POINTER(C.c_double), C.POINTER(C.c_float), C.c_float, C.c_void_p]),
+    "occl_median_fuse": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p]),
     "occl_sync": (C.c_int, [C.c_void_p]),
     "occl_release": (C.c_int, [C.c_void_p]),
     "occl_status_string": (C.c_char_p, [C.c_int]),
@@ -296,6 +297,16 @@ class Context:
                                 r.ctypes.data_as(C.POINTER(C.c_float)), float(beta), _ptr(M))
         self._check(st, "occl_zbuffer")
         return M
+
+    def occl_median_fuse(self, maps, D=None):
+        """maps: float32 [K, H, W] device tensor -> fused D [H, W] (NaN-ignoring median)."""
+        torch = self._torch
+        K, H, W = int(maps.shape[0]), int(maps.shape[1]), int(maps.shape[2])
+        if D is None:
+            D = torch.empty((H, W), dtype=torch.float32, device=maps.device)
+        st = lib().occl_median_fuse(self.h, _ptr(maps), K, H, W, _ptr(D))
+        self._check(st, "occl_median_fuse")
+        return D
 
     def occl_quality(self, pred, ref):
         """Eq. (7) on the GPU counts: precision, recall, F1, IoU (pooled)."""

@@ -340,3 +340,18 @@ def training_crops(seed: int, n_crops: int = 8, crop: int = 256, W: int = 1280, 
     ys = rng.integers(0, H - crop + 1, size=n_crops)
     xs = rng.integers(0, W - crop + 1, size=n_crops)
     return sc, list(zip(ys.tolist(), xs.tolist()))
+
+
+def fusion_maps(seed: int, D: np.ndarray, K: int = 8, noise: float = 0.3, outliers: float = 0.05,
+                holes: float = 0.03) -> np.ndarray:
+    """K noisy per-view disparity maps of a true centre map D (the input of the
+    median fusion): Gaussian noise, a fraction of gross outliers (uniform over
+    [0, 2 max D]) and a fraction of holes (NaN), independently per map."""
+    rng = np.random.default_rng(seed)
+    H, W = D.shape
+    maps = np.repeat(D[None].astype(np.float32), K, axis=0)
+    maps += rng.normal(0.0, noise, size=maps.shape).astype(np.float32)
+    out = rng.uniform(size=maps.shape) < outliers
+    maps[out] = rng.uniform(0.0, 2.0 * float(D.max()) + 1.0, size=int(out.sum())).astype(np.float32)
+    maps[rng.uniform(size=maps.shape) < holes] = np.nan
+    return np.ascontiguousarray(maps, dtype=np.float32)
