@@ -285,16 +285,17 @@ def bench_quality(ctx, n_frames: int = 4):
     from paper_2408_14050_amd import occl, scenes
     out = {"workload": f"c1 1280x960 x8 views seeds 1000..{1000 + n_frames - 1}",
            "reference": "forward-warping z-buffer (nearest target pixel, beta 0.5)"}
-    for name, mode in (("scan_len_config", 0), ("scan_len_eq3", -1)):
+    for name, mode, extra in (("scan_len_config", 0, 0), ("scan_len_eq3", -1, 0),
+                              ("scan_len_eq3_bilinear", -1, occl.FLAG_BILINEAR)):
         acc = [0, 0, 0, 0]
         per_frame = []
         for k in range(n_frames):
             sc = scenes.make_scene("c1", 1000 + k)
             D = torch.from_numpy(sc.D).cuda()
             if mode == 0:
-                prm = occl.params(**sc.params, scan_len_per_view=sc.scan_len)
+                prm = occl.params(**sc.params, scan_len_per_view=sc.scan_len, flags=extra)
             else:
-                prm = occl.params(**sc.params, scan_len=-1)
+                prm = occl.params(**sc.params, scan_len=-1, flags=extra)
             M = ctx.occl_detect(D, sc.angles, sc.ratios, prm)
             Z = ctx.occl_zbuffer(D, sc.angles, sc.ratios, sc.params["disp_thr"])
             q = ctx.occl_quality(M, Z)

@@ -69,6 +69,10 @@ typedef enum {
 #define OCCL_FLAG_SYNC 1u            /* synchronise the stream before returning */
 #define OCCL_FLAG_VALIDATE_INPUT 2u  /* check D for non-finite values first (synchronises) */
 #define OCCL_FLAG_USE_CNN 4u         /* learned tile proposal + exact fallback (needs weights) */
+#define OCCL_FLAG_BILINEAR 8u        /* variant: V read by bilinear interpolation of D at the real
+                                        scanline position (taps clamped into the frame; top row,
+                                        bottom row, then vertical blend, fp32 without FMA); kept
+                                        samples and marked pixels stay the nearest pixels */
 
 /* Detector parameters (Sec. 3: gamma of Eq. 2, zeta and beta of Eq. 5,
  * N of Eq. 5, L of Eqs. 3-4). */

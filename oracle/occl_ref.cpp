@@ -114,8 +114,32 @@ inline bool is_candidate(float E, float dot, float gamma) {
 }
 
 // Eq. (4) + the sampling step: the samples of one scanline, in g order.
+// Variant (not the paper's): V read by bilinear interpolation of D at the
+// scanline's real position (px, py) instead of at its nearest pixel.  The
+// four taps around (px, py) are clamped into the frame; with fx = px -
+// floor(px), fy = py - floor(py) (exact in fp32):
+//     top = (1 - fx) D(x0, y0) + fx D(x0 + 1, y0)
+//     bot = (1 - fx) D(x0, y0 + 1) + fx D(x0 + 1, y0 + 1)
+//     V   = (1 - fy) top + fy bot
+// (each product and sum rounded to fp32 in this order).  Which samples are
+// kept, and which pixel a hit marks, stay those of the nearest pixel (R5).
+float bilinear_sample(const float* D, int H, int W, float px, float py) {
+    const float fx0 = std::floor(px), fy0 = std::floor(py);
+    const float fx = px - fx0, fy = py - fy0;
+    const int x0 = (int)fx0, y0 = (int)fy0;
+    auto at = [&](int x, int y) {
+        x = std::min(std::max(x, 0), W - 1);
+        y = std::min(std::max(y, 0), H - 1);
+        return D[(size_t)y * W + x];
+    };
+    const float a = at(x0, y0), b = at(x0 + 1, y0), c = at(x0, y0 + 1), d = at(x0 + 1, y0 + 1);
+    const float top = (1.0f - fx) * a + fx * b;
+    const float bot = (1.0f - fx) * c + fx * d;
+    return (1.0f - fy) * top + fy * bot;
+}
+
 void build_scanline(const float* D, int H, int W, int cx, int cy, float c, float s,
-                    float r, int h, std::vector<Sample>& out) {
+                    float r, int h, std::vector<Sample>& out, bool bilinear = false) {
     out.clear();
     for (int g = -h; g <= h; ++g) {
         float gf = (float)g;
@@ -127,7 +151,7 @@ void build_scanline(const float* D, int H, int W, int cx, int cy, float c, float
         int iy = (int)std::rint(py);
         if (ix < 0 || ix >= W || iy < 0 || iy >= H) continue;  // R5: dropped
         Sample sm;
-        sm.V = D[(size_t)iy * W + ix];
+        sm.V = bilinear ? bilinear_sample(D, H, W, px, py) : D[(size_t)iy * W + ix];
         float rv = r * sm.V;
         float w = gf - rv;          // R1: W = g - r*V
         sm.W = w + 0.0f;            // -0 -> +0
@@ -304,10 +328,27 @@ int occl_ref_scan_len(const float* D, int H, int W, int n_views, const float* ra
  *            flip under a perturbation below 1e-4 px of any threshold margin
  *   n_cand   optional host int64 [n_views]: candidates per view
  * Returns 0, or -1 on an invalid argument. */
+int occl_ref_detect_ex(const float* D, int H, int W, int n_views, const double* angles,
+                       const float* ratios, const int* scan_len, float gamma, float beta,
+                       float zeta, int neighbours, unsigned char* M, unsigned char* tight,
+                       long long* n_cand, int flags);
+
 int occl_ref_detect(const float* D, int H, int W, int n_views, const double* angles,
                     const float* ratios, const int* scan_len, float gamma, float beta,
                     float zeta, int neighbours, unsigned char* M, unsigned char* tight,
                     long long* n_cand) {
+    return occl_ref_detect_ex(D, H, W, n_views, angles, ratios, scan_len, gamma, beta, zeta,
+                              neighbours, M, tight, n_cand, 0);
+}
+
+/* occl_ref_detect with variant flags: bit 0 = bilinear V sampling (see
+ * bilinear_sample; the tight map then covers the nearest-pixel decisions
+ * only). */
+int occl_ref_detect_ex(const float* D, int H, int W, int n_views, const double* angles,
+                       const float* ratios, const int* scan_len, float gamma, float beta,
+                       float zeta, int neighbours, unsigned char* M, unsigned char* tight,
+                       long long* n_cand, int flags) {
+    const bool bilinear = (flags & 1) != 0;
     if (!D || !angles || !ratios || !scan_len || !M || H < 1 || W < 1 || n_views < 1 ||
         neighbours < 1)
         return -1;
@@ -349,7 +390,7 @@ int occl_ref_detect(const float* D, int H, int W, int n_views, const double* ang
                                  (std::fabs(dot) < kTightEps && E[i] > gamma - kTightEps);
                 }
                 if (!cand && !cand_tight) continue;
-                build_scanline(D, H, W, x, y, c, s, r, h, smp);  // Eq. (4) + V
+                build_scanline(D, H, W, x, y, c, s, r, h, smp, bilinear);  // Eq. (4) + V
                 if (cand_tight) {
                     for (const Sample& sm : smp) Tv[(size_t)sm.iy * W + sm.ix] = 1;
                 }
@@ -502,6 +543,21 @@ int occl_ref_zbuffer(const float* D, int H, int W, int n_views, const double* an
         }
         for (size_t i = 0; i < HW; ++i) M[(size_t)v * HW + i] = (best[i] - D[i] > beta) ? 1 : 0;
     }
+    return 0;
+}
+
+/* The V of one scanline sample at real position (px, py): nearest pixel
+ * (bilinear = 0; the position must round into the frame) or the bilinear
+ * variant (bilinear = 1). */
+int occl_ref_sample(const float* D, int H, int W, float px, float py, int bilinear, float* V) {
+    if (!D || !V || H < 1 || W < 1) return -1;
+    if (bilinear) {
+        *V = bilinear_sample(D, H, W, px, py);
+        return 0;
+    }
+    const int ix = (int)std::rint(px), iy = (int)std::rint(py);
+    if (ix < 0 || ix >= W || iy < 0 || iy >= H) return -1;
+    *V = D[(size_t)iy * W + ix];
     return 0;
 }
 

@@ -39,6 +39,9 @@ def lib():
         L.occl_ref_confusion.argtypes = [u8, u8, C.c_longlong, i64]
         L.occl_ref_zbuffer.argtypes = [fp, C.c_int, C.c_int, C.c_int, dp, fp, C.c_float, u8]
         L.occl_ref_median_fuse.argtypes = [fp, C.c_int, C.c_longlong, fp]
+        L.occl_ref_detect_ex.argtypes = [fp, C.c_int, C.c_int, C.c_int, dp, fp, i32, C.c_float,
+                                         C.c_float, C.c_float, C.c_int, u8, u8, i64, C.c_int]
+        L.occl_ref_sample.argtypes = [fp, C.c_int, C.c_int, C.c_float, C.c_float, C.c_int, fp]
         L.occl_ref_scanline_pixels.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
                                                C.c_int, i32, i32, C.c_int]
         L.occl_ref_detect_window.argtypes = [fp, C.c_int, C.c_int, C.c_int, dp, fp, i32, C.c_float,
@@ -129,8 +132,9 @@ def scan_len(D, ratios, mode: int = 0):
 
 
 def detect(D, angles, ratios, scan_len, edge_thr=1.0, disp_thr=0.5, dist_thr=1.0,
-           neighbours=1, want_tight=False):
-    """Returns (M [V,H,W] uint8, tight or None, n_cand [V] int64)."""
+           neighbours=1, want_tight=False, bilinear=False):
+    """Returns (M [V,H,W] uint8, tight or None, n_cand [V] int64).
+    bilinear: the bilinear-V variant (occl_ref_detect_ex flag 1)."""
     D = _f32(D)
     H, W = D.shape
     a = np.ascontiguousarray(np.atleast_1d(angles), dtype=np.float64)
@@ -140,10 +144,10 @@ def detect(D, angles, ratios, scan_len, edge_thr=1.0, disp_thr=0.5, dist_thr=1.0
     M = np.empty((V, H, W), np.uint8)
     T = np.empty((V, H, W), np.uint8) if want_tight else None
     nc = np.zeros(V, np.int64)
-    rc = lib().occl_ref_detect(_p(D, C.c_float), H, W, V, _p(a, C.c_double), _p(r, C.c_float),
-                               _p(Ls, C.c_int), float(edge_thr), float(disp_thr), float(dist_thr),
-                               int(neighbours), _p(M, C.c_ubyte), _p(T, C.c_ubyte),
-                               _p(nc, C.c_longlong))
+    rc = lib().occl_ref_detect_ex(_p(D, C.c_float), H, W, V, _p(a, C.c_double), _p(r, C.c_float),
+                                  _p(Ls, C.c_int), float(edge_thr), float(disp_thr), float(dist_thr),
+                                  int(neighbours), _p(M, C.c_ubyte), _p(T, C.c_ubyte),
+                                  _p(nc, C.c_longlong), 1 if bilinear else 0)
     if rc != 0:
         raise ValueError("invalid argument to occl_ref_detect")
     return M, T, nc
@@ -218,3 +222,14 @@ def median_fuse(maps):
     if rc != 0:
         raise ValueError("invalid argument to occl_ref_median_fuse")
     return out
+
+
+def sample(D, px, py, bilinear=True):
+    """V of one scanline sample at real position (px, py) (occl_ref_sample)."""
+    D = _f32(D)
+    H, W = D.shape
+    v = C.c_float()
+    rc = lib().occl_ref_sample(_p(D, C.c_float), H, W, float(px), float(py), int(bilinear), C.byref(v))
+    if rc != 0:
+        raise ValueError("sample outside the frame")
+    return np.float32(v.value)

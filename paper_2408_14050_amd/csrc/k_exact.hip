@@ -436,8 +436,23 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
         const int ix = (int)rintf(px);
         const int iy = (int)rintf(py);
         const bool valid = (e < n) & (ix >= 0) & (ix < W) & (iy >= 0) & (iy < H);
-        const int cxi = min(max(ix, 0), W - 1), cyi = min(max(iy, 0), H - 1);
-        const float Vr = D[(size_t)cyi * W + cxi];
+        float Vr;
+        if (th.bilinear) {  // variant: bilinear V at (px, py), taps clamped into the frame
+            const float fx0 = floorf(px), fy0 = floorf(py);
+            const float fx = __fsub_rn(px, fx0), fy = __fsub_rn(py, fy0);
+            const int x0 = (int)fx0, y0 = (int)fy0;
+            const int xa = min(max(x0, 0), W - 1), xb = min(max(x0 + 1, 0), W - 1);
+            const int ya = min(max(y0, 0), H - 1), yb = min(max(y0 + 1, 0), H - 1);
+            const float a = D[(size_t)ya * W + xa], b = D[(size_t)ya * W + xb];
+            const float cc = D[(size_t)yb * W + xa], d = D[(size_t)yb * W + xb];
+            const float gx = __fsub_rn(1.0f, fx), gy = __fsub_rn(1.0f, fy);
+            const float top = __fadd_rn(__fmul_rn(gx, a), __fmul_rn(fx, b));
+            const float bot = __fadd_rn(__fmul_rn(gx, cc), __fmul_rn(fx, d));
+            Vr = __fadd_rn(__fmul_rn(gy, top), __fmul_rn(fy, bot));
+        } else {
+            const int cxi = min(max(ix, 0), W - 1), cyi = min(max(iy, 0), H - 1);
+            Vr = D[(size_t)cyi * W + cxi];
+        }
         const float V = valid ? Vr : 0.0f;
         const float w = valid ? __fsub_rn(gf, __fmul_rn(r, Vr)) : __int_as_float(0x7fc00000);
         L.Vin[e] = V;

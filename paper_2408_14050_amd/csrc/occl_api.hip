@@ -471,6 +471,7 @@ Thresholds occl::make_thresholds(const occl_params* p) {
     th.zeta = p->dist_thr;
     int ns = (p->neighbours + 1) / 2;
     th.ns = ns < 1 ? 1 : ns;
+    th.bilinear = (p->flags & OCCL_FLAG_BILINEAR) ? 1 : 0;
     return th;
 }
 

@@ -65,6 +65,7 @@ struct Thresholds {
     float beta;    // disparity threshold (Eq. 5)
     float zeta;    // distance threshold (Eq. 5)
     int ns;        // neighbours per side, max(1, ceil(N/2))
+    int bilinear;  // 1: V by bilinear interpolation at the real sample position (variant)
 };
 
 struct ListLayout {

@@ -24,6 +24,7 @@ OCCL_MAX_SCAN_LEN = 1023
 FLAG_SYNC = 1
 FLAG_VALIDATE_INPUT = 2
 FLAG_USE_CNN = 4
+FLAG_BILINEAR = 8
 
 
 class OcclError(RuntimeError):
