@@ -106,7 +106,8 @@ occl_status occl_init(occl_ctx** out, int device, void* hip_stream, size_t max_p
 /* One frame, n_views views.
  *   D          device fp32 [H][W], row-major contiguous (16-byte alignment and W % 4 == 0
  *              select the vectorised path; anything else is still correct)
- *   H, W       >= 0; H*W == 0 or n_views == 0 is a valid empty call (nothing enqueued)
+ *   H, W       0..65535 (larger: OCCL_ERR_UNSUPPORTED); H*W == 0 or n_views == 0 is a valid
+ *              empty call (nothing enqueued)
  *   n_views    0..OCCL_MAX_VIEWS
  *   angles_deg host double [n_views], finite
  *   ratios     host float [n_views], finite and > 0

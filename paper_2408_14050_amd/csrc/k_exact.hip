@@ -205,7 +205,7 @@ __device__ void edge_block(const FrameDesc& f, int bx, int by, int n_views, cons
         }
         if (__ballot(any)) {
             const int band = by / f.ll.block_rows_per_copy;
-            const uint32_t pix = (uint32_t)y * (uint32_t)W + (uint32_t)x0;
+            const uint32_t pix = ((uint32_t)y << 16) | (uint32_t)x0;  // packed (y, x); W, H <= 65535
             // Views go in chunks of kViewChunk: the candidate bits of every view
             // of the chunk first, then one atomic instruction in which lane i
             // reserves view v0 + i's entries (a single round trip for the
@@ -624,8 +624,8 @@ __device__ __forceinline__ void scan_item(const FrameDesc& f, int v, uint32_t pi
                                           const ViewTable& vt, const Thresholds& th,
                                           const WaveLds& L, int lane) {
     const int W = f.W, H = f.H;
-    const int cy = (int)(pix / (uint32_t)W);
-    const int cx = (int)(pix - (uint32_t)cy * (uint32_t)W);
+    const int cy = (int)(pix >> 16);  // list entries are packed (y << 16) | x
+    const int cx = (int)(pix & 0xffffu);
     const int h = f.h[v];
     uint8_t* Mv = f.M + (size_t)v * H * W;
     TileView tv{nullptr, f.tiles_x};
@@ -659,11 +659,18 @@ __global__ __launch_bounds__(64 * waves_per_block<KMAX>()) void k_scanlines(
     __shared__ uint32_t okeys[WPB][64 * KMAX];
     __shared__ int runs[WPB][kMaxRunsCap + 1];
     __shared__ int pre[kMaxSegments + 1];
+    __shared__ int segvs[kMaxSegments];  // class segment j: (view << 16) | physical segment
     const int C = f.ll.copies;
     const int seg0 = f.cls_start[cls] * C;
     const int nseg = (f.cls_start[cls + 1] - f.cls_start[cls]) * C;
     const int base = f.prefix[seg0];
-    for (int j = threadIdx.x; j <= nseg; j += NT) pre[j] = f.prefix[seg0 + j] - base;
+    for (int j = threadIdx.x; j <= nseg; j += NT) {
+        pre[j] = f.prefix[seg0 + j] - base;
+        if (j < nseg) {
+            const int v = f.vord[f.cls_start[cls] + j / C];
+            segvs[j] = (v << 16) | (v * C + j % C);
+        }
+    }
     __syncthreads();
     const int total = pre[nseg];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -684,8 +691,8 @@ __global__ __launch_bounds__(64 * waves_per_block<KMAX>()) void k_scanlines(
         }
         for (int t = g0; t < g1; ++t) {
             while (lo + 1 < nseg && pre[lo + 1] <= t) ++lo;
-            int v, seg;
-            segment_of(f, cls, lo, &v, &seg);
+            const int sv = segvs[lo];
+            const int v = sv >> 16, seg = sv & 0xffff;
             const uint32_t pix = f.lists[(size_t)seg * f.ll.cap + (size_t)(t - pre[lo])];
             scan_item<KMAX>(f, v, pix, vt, th, L, lane);
         }

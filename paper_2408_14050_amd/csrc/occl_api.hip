@@ -491,7 +491,7 @@ occl_status detect_impl(occl_ctx* ctx, const float* D, int32_t H, int32_t W, int
     if ((size_t)H * W == 0 || n_views == 0) return OCCL_OK;
     if (!D || !M) return ctx->fail(OCCL_ERR_INVALID_ARG, "D or M is NULL");
     if (routed && !logits) return ctx->fail(OCCL_ERR_INVALID_ARG, "logits is NULL");
-    if (H > 65535 || W > 65535 * kEdgeCols) return ctx->fail(OCCL_ERR_UNSUPPORTED, "frame too large");
+    if (H > 65535 || W > 65535) return ctx->fail(OCCL_ERR_UNSUPPORTED, "frame too large");
     const bool cnn = !routed && (params->flags & OCCL_FLAG_USE_CNN);
     if (cnn && !ctx->cnn_ready()) return ctx->fail(OCCL_ERR_NO_MODEL, "USE_CNN without loaded weights");
     hipError_t e = hipSetDevice(ctx->device);

@@ -178,7 +178,7 @@ occl_status prepare_batch(occl_ctx* ctx, int32_t n_frames, const occl_frame* fra
     for (int f = 0; f < n_frames; ++f) {
         const occl_frame& fr = frames[f];
         if (fr.H < 0 || fr.W < 0) return ctx->fail(OCCL_ERR_INVALID_ARG, "negative frame size");
-        if (fr.H > 65535 || fr.W > 65535 * kEdgeCols || (size_t)fr.H * fr.W > ((size_t)1 << 31))
+        if (fr.H > 65535 || fr.W > 65535 || (size_t)fr.H * fr.W > ((size_t)1 << 31))
             return ctx->fail(OCCL_ERR_UNSUPPORTED, "frame too large");
         if ((size_t)fr.H * fr.W > 0 && n_views > 0 && (!fr.D || !fr.M))
             return ctx->fail(OCCL_ERR_INVALID_ARG, "frame D or M is NULL");
@@ -304,7 +304,7 @@ extern "C" occl_status occl_autotune(occl_ctx* ctx, const float* D, int32_t H, i
     occl_status s = ctx->check_params(params, n_views, angles_deg, ratios);
     if (s != OCCL_OK) return s;
     if (H < 1 || W < 1 || n_views < 1 || !D || !M) return ctx->fail(OCCL_ERR_INVALID_ARG, "frame");
-    if (H > 65535 || W > 65535 * kEdgeCols || (size_t)H * W > ((size_t)1 << 31))
+    if (H > 65535 || W > 65535 || (size_t)H * W > ((size_t)1 << 31))
         return ctx->fail(OCCL_ERR_UNSUPPORTED, "frame too large");
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return ctx->hip_fail(e, "hipSetDevice");
