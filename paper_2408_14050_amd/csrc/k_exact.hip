@@ -644,8 +644,10 @@ __device__ __forceinline__ void scan_item(const FrameDesc& f, int v, uint32_t pi
 // its physical segment index.
 __device__ __forceinline__ void segment_of(const FrameDesc& f, int cls, int lo, int* v, int* seg) {
     const int C = f.ll.copies;
-    *v = f.vord[f.cls_start[cls] + lo / C];
-    *seg = *v * C + lo % C;
+    // lo / C (lo < kMaxSegments); ceil(2^32 / C) does not fit 32 bits for C = 1
+    const int q = C == 1 ? lo : (int)__umulhi((uint32_t)lo, f.copies_magic);
+    *v = f.vord[f.cls_start[cls] + q];
+    *seg = *v * C + (lo - q * C);
 }
 
 // One frame, the views of scan class cls: a flat walk over every
@@ -822,6 +824,9 @@ void describe_frame(FrameDesc* f, const float* D, uint8_t* M, int H, int W, int 
     f->H = H;
     f->W = W;
     f->ll = make_list_layout(H, W, n_views, edge_rows);
+    f->copies_magic = f->ll.copies > 1
+                          ? (uint32_t)(((1ull << 32) + (uint64_t)f->ll.copies - 1) / (uint64_t)f->ll.copies)
+                          : 0u;  // unused for one copy
     f->gx = (W + kEdgeCols - 1) / kEdgeCols;
     f->gy = (H + edge_rows - 1) / edge_rows;
     f->block_begin = 0;

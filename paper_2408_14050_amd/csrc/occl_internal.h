@@ -87,6 +87,8 @@ struct FrameDesc {
     uint32_t* lists;
     int32_t* counts;
     int32_t* prefix;
+    uint32_t copies_magic;            // ceil(2^32 / ll.copies) for copies > 1: umulhi(j, magic) = j / copies
+                                      // for j < 2^16
     int gx, gy;                       // edge-pass blocks along x / y
     int block_begin;                  // first flat edge-pass block (batched launch)
     int h[OCCL_MAX_VIEWS];            // half scan length floor(L/2) per view
