@@ -290,6 +290,15 @@ def test_invalid_arguments_have_no_side_effects(gctx, torch):
                                 np.ones(2, np.float32).ctypes.data_as(C.POINTER(C.c_float)),
                                 C.byref(occl.params(**good)), C.c_void_p(M.data_ptr()))
     assert st == -1
+    # frames wider or taller than 65535 (packed candidate coordinates) are
+    # refused before anything is enqueued; the sizes are checked first, so
+    # small buffers suffice
+    for H, W in ((2, 65536), (65536, 2)):
+        st = occl.lib().occl_detect(gctx.h, C.c_void_p(D.data_ptr()), H, W, 2,
+                                    np.zeros(2).ctypes.data_as(C.POINTER(C.c_double)),
+                                    np.ones(2, np.float32).ctypes.data_as(C.POINTER(C.c_float)),
+                                    C.byref(occl.params(**good)), C.c_void_p(M.data_ptr()))
+        assert st == -4, (H, W, st)
     torch.cuda.synchronize()
     assert (M == 7).all()
     with pytest.raises(occl.OcclError):
