@@ -1,6 +1,6 @@
 """The oracle's pins are sensitive: each plausible slip planted in a copy of
 the oracle source (on the CPU, in a temporary directory) must make at least
-one pin of test_oracle_pins.py fail.
+one CPU pin (the files in PIN_FILES) fail.
 
 The one slip no pin can see is the tie rule of rounding at exact half-pixel
 coordinates (round half to even vs half up): the paper only says "nearest",
@@ -35,14 +35,26 @@ MUTANTS = {
     "truncate_coordinate": ("int ix = (int)std::rint(px);", "int ix = (int)std::floor(px);"),
     "ratio_dropped": ("float rv = r * sm.V;\n        float w = gf - rv;          // R1",
                       "float rv = sm.V;\n        float w = gf - rv;          // R1"),
-    "V_index_transposed": ("sm.V = D[(size_t)iy * W + ix];", "sm.V = D[((size_t)ix * W + iy) % ((size_t)H * W)];"),
+    "V_index_transposed": (": D[(size_t)iy * W + ix];", ": D[((size_t)ix * W + iy) % ((size_t)H * W)];"),
+    "bilinear_x_weights_swapped": ("const float top = (1.0f - fx) * a + fx * b;",
+                                   "const float top = fx * a + (1.0f - fx) * b;"),
     "direction_cos_sin_swapped": ("cb = (float)std::cos(b * deg);\n        sb = (float)std::sin(b * deg);",
                                   "sb = (float)std::cos(b * deg);\n        cb = (float)std::sin(b * deg);"),
     "successor_only": ("for (int d = -ns; d <= ns; ++d) {\n            if (d == 0) continue;\n            int j = k + d;\n            if (j < 0 || j >= n) continue;\n            float dw = std::fabs(smp[k].W - smp[j].W);\n            float dv = smp[j].V - smp[k].V;\n            if (dw < zeta && dv > beta) ++O;",
                        "for (int d = 1; d <= ns; ++d) {\n            int j = k + d;\n            if (j < 0 || j >= n) continue;\n            float dw = std::fabs(smp[k].W - smp[j].W);\n            float dv = smp[j].V - smp[k].V;\n            if (dw < zeta && dv > beta) ++O;"),
     "mask_written_at_candidate": ("if (hit[k]) Mv[(size_t)smp[k].iy * W + smp[k].ix] = 1;",
                                   "if (hit[k]) Mv[(size_t)y * W + x] = 1;"),
+    # forward-warping ground truth
+    "zbuffer_target_sign": ("const long long tx = (long long)std::nearbyint((float)x - t * c);",
+                            "const long long tx = (long long)std::nearbyint((float)x + t * c);"),
+    "zbuffer_non_strict": ("(best[i] - D[i] > beta) ? 1 : 0;", "(best[i] - D[i] >= beta) ? 1 : 0;"),
+    # median fusion
+    "median_even_takes_lower": ("(v[m / 2 - 1] + v[m / 2]) * 0.5f", "v[m / 2 - 1]"),
+    "median_keeps_nan": ("if (!std::isnan(x)) v.push_back(x);", "v.push_back(x);"),
 }
+
+# every CPU pin file that exercises the oracle
+PIN_FILES = ("test_oracle_pins.py", "test_bilinear.py", "test_quality_oracle.py", "test_fusion.py")
 
 
 @pytest.mark.slow
@@ -56,11 +68,11 @@ def test_pins_catch_mutant(name, tmp_path):
     shutil.copytree(os.path.join(ROOT, "paper_2408_14050_amd"), tmp_path / "paper_2408_14050_amd",
                     ignore=shutil.ignore_patterns("*.so", "__pycache__", "csrc", "*.tmp"))
     os.makedirs(tmp_path / "tests")
-    for f in ("conftest.py", "test_oracle_pins.py"):
+    for f in ("conftest.py",) + PIN_FILES:
         shutil.copy(os.path.join(ROOT, "tests", f), tmp_path / "tests" / f)
     shutil.copytree(os.path.join(ROOT, "tests", "golden"), tmp_path / "tests" / "golden")
     (tmp_path / "oracle" / "occl_ref.cpp").write_text(src.replace(old, new))
-    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        "tests/test_oracle_pins.py"], cwd=tmp_path, capture_output=True, text=True,
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider", "-m", "not gpu"]
+                       + [f"tests/{f}" for f in PIN_FILES], cwd=tmp_path, capture_output=True, text=True,
                        timeout=300)
     assert r.returncode != 0, f"mutant {name} survived every pin:\n{r.stdout[-2000:]}"

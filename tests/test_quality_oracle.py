@@ -112,3 +112,16 @@ def test_method_against_ground_truth_on_c1_statistics(ref):
     Mc, _, _ = ref.detect_scene(sc)
     qc = ref.quality(Mc, Z)
     assert qc["recall"] < 0.8 and qc["precision"] > 0.85, qc
+
+
+def test_zbuffer_strict_threshold(ref):
+    """A disparity step of exactly beta does not occlude (the comparison is
+    strict, like Eq. (5)'s); a hair above it does (a 1-pixel strip)."""
+    H, W = 20, 30
+    D = np.full((H, W), 2.0, np.float32)
+    D[5:15, 10:20] = 3.0
+    assert ref.zbuffer(D, [0], [1.0], 1.0).sum() == 0
+    Z = ref.zbuffer(D, [0], [1.0], 0.999)[0]
+    E = np.zeros((H, W), np.uint8)
+    E[5:15, 9] = 1
+    np.testing.assert_array_equal(Z, E)
