@@ -217,6 +217,27 @@ class Context:
         self._check(st, "occl_detect")
         return M
 
+    def occl_detect_prepared(self, angles, ratios, prm: occl_params):
+        """occl_detect with the views and parameters marshalled once: returns
+        f(D, M) that calls the library with only the frame pointers and sizes
+        per call (for tight loops over many frames of the same views)."""
+        a, r = self._views(angles, ratios)
+        ap = a.ctypes.data_as(C.POINTER(C.c_double))
+        rp = r.ctypes.data_as(C.POINTER(C.c_float))
+        pr = C.byref(prm)
+        L, h, nv = lib(), self.h, int(a.shape[0])
+        keep = (a, r, prm)
+
+        def detect(D, M):
+            st = L.occl_detect(h, C.c_void_p(D.data_ptr()), int(D.shape[0]), int(D.shape[1]), nv,
+                               ap, rp, pr, C.c_void_p(M.data_ptr()))
+            if st != OCCL_OK:
+                self._check(st, "occl_detect")
+            return M
+
+        detect._keep = keep  # the marshalled arrays live as long as the function
+        return detect
+
     @staticmethod
     def _frames(frames):
         arr = (occl_frame * max(1, len(frames)))()

@@ -350,3 +350,30 @@ def test_integer_maps_with_ties(gctx, torch, ref, seed):
         M, nc = run_gpu(gctx, torch, D, angles, ratios, L, counts=True, neighbours=N, dist_thr=zeta)
         np.testing.assert_array_equal(nc, nc_ref)
         assert_parity(M, M_ref, None, f"integer seed {seed} N={N} zeta={zeta}")
+
+
+def test_prepared_call_and_frames_in_flight(torch, ref):
+    """The prepared per-frame call, and frames in flight on three contexts
+    with their own streams (the throughput launch configuration), give the
+    oracle's masks for every frame, also with frames of different maps
+    interleaved across the streams."""
+    from paper_2408_14050_amd import occl
+    scs = [scenes.make_scene("c0", 60 + i) for i in range(6)]
+    sc0 = scs[0]
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    ctxs = [occl.Context(0, stream=s) for s in streams]
+    prm = occl.params(scan_len_per_view=sc0.scan_len, **sc0.params)
+    dets = [c.occl_detect_prepared(sc0.angles, sc0.ratios, prm) for c in ctxs]
+    Ds = [torch.from_numpy(np.ascontiguousarray(s.D)).cuda() for s in scs]
+    torch.cuda.synchronize()
+    Ms = [torch.empty((len(sc0.angles),) + s.D.shape, dtype=torch.uint8, device="cuda") for s in scs]
+    for rep in range(3):
+        for i in range(len(scs)):
+            dets[i % 3](Ds[i], Ms[i])
+    for c in ctxs:
+        c.occl_sync()
+    for s, M in zip(scs, Ms):
+        M_ref, _, _ = ref.detect(s.D, sc0.angles, sc0.ratios, sc0.scan_len, **sc0.params)
+        assert_parity(M.cpu().numpy(), M_ref, None, "frames in flight")
+    for c in ctxs:
+        c.occl_release()
