@@ -203,6 +203,28 @@ __device__ void edge_block(const FrameDesc& f, int bx, int by, int n_views, cons
             strong[j] = live && (x < W) && (q >= q_min);
             any |= strong[j];
         }
+        // Every mask byte of the segment starts at 0 (a routed frame's filled
+        // tiles at their fill value).  The stores are issued while the list
+        // reservation's atomic is in flight.
+        auto clear_mask = [&]() {
+            if (!live) return;
+            const size_t HW = (size_t)H * W;
+            const int tiles_y = (H + kTile - 1) / kTile;
+            for (int v = 0; v < n_views; ++v) {
+                uint8_t* mrow = f.M + v * HW + (size_t)y * W;
+                const uint8_t fill =
+                    f.tstate ? (f.tstate[((size_t)v * tiles_y + y / kTile) * f.tiles_x + x0 / kTile] == 1)
+                             : 0;
+                if (vec) {
+                    *reinterpret_cast<uint32_t*>(mrow + x0) = 0x01010101u * fill;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (x0 + j < W) mrow[x0 + j] = fill;
+                }
+            }
+        };
+        bool cleared = false;  // uniform
         if (__ballot(any)) {
             const int band = by / f.ll.block_rows_per_copy;
             const uint32_t pix = ((uint32_t)y << 16) | (uint32_t)x0;  // packed (y, x); W, H <= 65535
@@ -243,6 +265,10 @@ __device__ void edge_block(const FrameDesc& f, int bx, int by, int n_views, cons
                 int my_base = 0;
                 if (my_tot > 0)
                     my_base = atomicAdd(&f.counts[((v0 + lane) * f.ll.copies + band) * kCounterPad], my_tot);
+                if (!cleared) {
+                    clear_mask();
+                    cleared = true;
+                }
                 // every base into a scalar before the first append (the appends'
                 // stores would otherwise sit between the atomic and its reads)
                 int bs[kViewChunk];
@@ -260,24 +286,7 @@ __device__ void edge_block(const FrameDesc& f, int bx, int by, int n_views, cons
                 }
             }
         }
-        if (live) {
-            const size_t HW = (size_t)H * W;
-            const int tiles_y = (H + kTile - 1) / kTile;
-            for (int v = 0; v < n_views; ++v) {
-                uint8_t* mrow = f.M + v * HW + (size_t)y * W;
-                // a routed frame starts filled tiles at their fill value
-                const uint8_t fill =
-                    f.tstate ? (f.tstate[((size_t)v * tiles_y + y / kTile) * f.tiles_x + x0 / kTile] == 1)
-                             : 0;
-                if (vec) {
-                    *reinterpret_cast<uint32_t*>(mrow + x0) = 0x01010101u * fill;
-                } else {
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (x0 + j < W) mrow[x0 + j] = fill;
-                }
-            }
-        }
+        if (!cleared) clear_mask();
     }
     if constexpr (!kFinish) return;  // the batched path finishes frames in k_finish_frames
     // The last block of the frame turns the counters into the frame's prefix.
@@ -807,8 +816,13 @@ ListLayout make_list_layout(int H, int W, int n_views, int edge_rows) {
     ListLayout ll;
     ll.edge_rows = edge_rows;
     const int block_rows = (H + edge_rows - 1) / edge_rows;
-    int copies = kMaxSegments / (n_views > 0 ? n_views : 1);
-    if (copies > kMaxCopies) copies = kMaxCopies;
+    // Bands of block rows: enough that one list counter takes the atomics of
+    // about kWavesPerBand edge-pass wavefronts, no more (every extra segment
+    // costs the frame's prefix and the scanline pass's segment tables).
+    const long long waves = (long long)block_rows * edge_rows * ((W + kEdgeCols - 1) / kEdgeCols);
+    const long long want = (waves + kWavesPerBand - 1) / kWavesPerBand;
+    int copies = want < kMaxCopies ? (int)want : kMaxCopies;
+    if (copies > kMaxSegments / (n_views > 0 ? n_views : 1)) copies = kMaxSegments / (n_views > 0 ? n_views : 1);
     if (copies > block_rows) copies = block_rows;
     if (copies < 1) copies = 1;
     ll.block_rows_per_copy = (block_rows + copies - 1) / copies;

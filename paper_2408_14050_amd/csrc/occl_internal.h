@@ -21,10 +21,14 @@ constexpr int kMaxEdgeRows = 16;
 // segments by horizontal bands of edge-pass block rows; each segment has its
 // own counter (on its own 128-byte line, so the appends of different bands
 // never contend) and room for every pixel of its band (`cap`).  Entries are
-// pixel indices y*W + x in no particular order: the mask is an OR of
-// scanline hits, so the order never changes the result.
+// packed pixel coordinates (y << 16) | x in no particular order: the mask is
+// an OR of scanline hits, so the order never changes the result.
 constexpr int kCounterPad = 32;    // int32 stride between counters (128 bytes)
 constexpr int kMaxCopies = 64;
+#ifndef OCCL_WAVES_PER_BAND
+#define OCCL_WAVES_PER_BAND 200
+#endif
+constexpr int kWavesPerBand = OCCL_WAVES_PER_BAND;  // edge-pass wavefronts per list segment (target)
 constexpr int kMaxSegments = 1024; // views x copies
 // Per-frame "counts" workspace: kMaxSegments padded counters, then the edge
 // pass's completion counters (one top counter and kDoneGroups group
