@@ -13,16 +13,37 @@ __device__ __forceinline__ uint32_t ford(float w) {
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-__global__ void k_stats_init(uint32_t* dev) {
-    if (threadIdx.x == 0) {
-        dev[0] = 0xffffffffu;  // running min (orderable)
-        dev[1] = 0u;           // running max (orderable)
-        dev[2] = 0u;           // non-finite count
+// Statistics of D in two launches without atomics: per-block partials
+// (min, max as orderable uints, non-finite count), then one block folds them.
+__device__ __forceinline__ void fold_stats(uint32_t& mn, uint32_t& mx, uint32_t& bad) {
+    __shared__ uint32_t red[3][4];
+    for (int m = 32; m > 0; m >>= 1) {
+        const uint32_t a = (uint32_t)__shfl_xor((int)mn, m, 64);
+        const uint32_t b = (uint32_t)__shfl_xor((int)mx, m, 64);
+        const uint32_t c = (uint32_t)__shfl_xor((int)bad, m, 64);
+        mn = a < mn ? a : mn;
+        mx = b > mx ? b : mx;
+        bad += c;
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = mn;
+        red[1][w] = mx;
+        red[2][w] = bad;
+    }
+    __syncthreads();
+    mn = red[0][0];
+    mx = red[1][0];
+    bad = red[2][0];
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+        mn = red[0][k] < mn ? red[0][k] : mn;
+        mx = red[1][k] > mx ? red[1][k] : mx;
+        bad += red[2][k];
     }
 }
 
 __global__ __launch_bounds__(256) void k_stats(const float* __restrict__ D, size_t n,
-                                               uint32_t* __restrict__ dev) {
+                                               uint32_t* __restrict__ partial) {
     uint32_t mn = 0xffffffffu, mx = 0u, bad = 0u;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x) {
@@ -35,18 +56,28 @@ __global__ __launch_bounds__(256) void k_stats(const float* __restrict__ D, size
         mn = o < mn ? o : mn;
         mx = o > mx ? o : mx;
     }
-    for (int m = 32; m > 0; m >>= 1) {
-        const uint32_t a = (uint32_t)__shfl_xor((int)mn, m, 64);
-        const uint32_t b = (uint32_t)__shfl_xor((int)mx, m, 64);
-        const uint32_t c = (uint32_t)__shfl_xor((int)bad, m, 64);
-        mn = a < mn ? a : mn;
-        mx = b > mx ? b : mx;
-        bad += c;
+    fold_stats(mn, mx, bad);
+    if (threadIdx.x == 0) {
+        partial[(size_t)blockIdx.x * 3 + 0] = mn;
+        partial[(size_t)blockIdx.x * 3 + 1] = mx;
+        partial[(size_t)blockIdx.x * 3 + 2] = bad;
     }
-    if ((threadIdx.x & 63) == 0) {
-        atomicMin(&dev[0], mn);
-        atomicMax(&dev[1], mx);
-        if (bad) atomicAdd(&dev[2], bad);
+}
+
+__global__ __launch_bounds__(256) void k_stats_sum(const uint32_t* __restrict__ partial, int n_blocks,
+                                                   uint32_t* __restrict__ out) {
+    uint32_t mn = 0xffffffffu, mx = 0u, bad = 0u;
+    for (int b = threadIdx.x; b < n_blocks; b += blockDim.x) {
+        const uint32_t a = partial[(size_t)b * 3], c = partial[(size_t)b * 3 + 1];
+        mn = a < mn ? a : mn;
+        mx = c > mx ? c : mx;
+        bad += partial[(size_t)b * 3 + 2];
+    }
+    fold_stats(mn, mx, bad);
+    if (threadIdx.x == 0) {
+        out[0] = mn;
+        out[1] = mx;
+        out[2] = bad;
     }
 }
 
@@ -130,16 +161,27 @@ __global__ __launch_bounds__(256) void k_confusion(const uint8_t* __restrict__ p
     }
 }
 
-__global__ __launch_bounds__(64) void k_confusion_sum(const unsigned long long* __restrict__ partial,
-                                                      int n_blocks, size_t n,
-                                                      unsigned long long* __restrict__ out) {
-    if (threadIdx.x < 3) {
-        unsigned long long t = 0;
-        for (int b = 0; b < n_blocks; ++b) t += partial[(size_t)b * 3 + threadIdx.x];
-        out[threadIdx.x] = t;
-    }
+// Integer sums, so the fold order never changes the result.
+__global__ __launch_bounds__(256) void k_confusion_sum(const unsigned long long* __restrict__ partial,
+                                                       int n_blocks, size_t n,
+                                                       unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long red[3][4];
+    unsigned long long t[3] = {0, 0, 0};
+    for (int b = threadIdx.x; b < n_blocks; b += blockDim.x)
+        for (int j = 0; j < 3; ++j) t[j] += partial[(size_t)b * 3 + j];
+    for (int m = 32; m > 0; m >>= 1)
+        for (int j = 0; j < 3; ++j) t[j] += __shfl_xor(t[j], m, 64);
+    if ((threadIdx.x & 63) == 0)
+        for (int j = 0; j < 3; ++j) red[j][threadIdx.x >> 6] = t[j];
     __syncthreads();
-    if (threadIdx.x == 0) out[3] = n - out[0] - out[1] - out[2];
+    if (threadIdx.x == 0) {
+        for (int j = 0; j < 3; ++j) {
+            t[j] = 0;
+            for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t[j] += red[j][k];
+            out[j] = t[j];
+        }
+        out[3] = n - t[0] - t[1] - t[2];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -349,8 +391,10 @@ inline int grid_for(size_t n, int per_block, int cap) {
 }  // namespace
 
 hipError_t launch_scan_stats(hipStream_t st, const float* D, size_t n, uint32_t* dev) {
-    hipLaunchKernelGGL(k_stats_init, dim3(1), dim3(64), 0, st, dev);
-    hipLaunchKernelGGL(k_stats, dim3(grid_for(n, 256 * 8, 2048)), dim3(256), 0, st, D, n, dev);
+    // dev: 3 results, then room for kStatsBlocks * 3 partials
+    const int nb = grid_for(n, 256 * 8, kStatsBlocks);
+    hipLaunchKernelGGL(k_stats, dim3(nb), dim3(256), 0, st, D, n, dev + 3);
+    hipLaunchKernelGGL(k_stats_sum, dim3(1), dim3(256), 0, st, dev + 3, nb, dev);
     return hipGetLastError();
 }
 
@@ -443,7 +487,7 @@ hipError_t launch_confusion(hipStream_t st, const uint8_t* pred, const uint8_t* 
     // dev4: 4 results, then room for kConfusionBlocks * 3 partials
     const int nb = grid_for(n, 256 * 16 * 4, kConfusionBlocks);
     hipLaunchKernelGGL(k_confusion, dim3(nb), dim3(256), 0, st, pred, ref, n, dev4 + 4);
-    hipLaunchKernelGGL(k_confusion_sum, dim3(1), dim3(64), 0, st, dev4 + 4, nb, n, dev4);
+    hipLaunchKernelGGL(k_confusion_sum, dim3(1), dim3(256), 0, st, dev4 + 4, nb, n, dev4);
     return hipGetLastError();
 }
 

@@ -270,7 +270,7 @@ occl_status occl_ctx::check_params(const occl_params* p, int n_views, const doub
 // Reads min / max / non-finite count of D back to the host (synchronises).
 occl_status occl_ctx::d_stats(const float* D, size_t n, float* mn, float* mx, uint32_t* bad) {
     void* dev;
-    occl_status s = ensure("stats", 64, &dev);
+    occl_status s = ensure("stats", (3 + 3 * (size_t)kStatsBlocks) * sizeof(uint32_t), &dev);
     if (s != OCCL_OK) return s;
     hipError_t e = launch_scan_stats(stream, D, n, (uint32_t*)dev);
     if (e != hipSuccess) return hip_fail(e, "scan_stats");

@@ -143,6 +143,9 @@ Thresholds make_thresholds(const occl_params* p);
 
 // ---- helpers (k_util.hip) ---------------------------------------------------
 // min / max / non-finite count of D into dev[0..2] (orderable uint32 / count).
+// min / max (orderable uints) and non-finite count of D into dev[0..2]; dev
+// holds 3 + 3 * kStatsBlocks uint32
+constexpr int kStatsBlocks = 1024;
 hipError_t launch_scan_stats(hipStream_t st, const float* D, size_t n, uint32_t* dev);
 
 hipError_t launch_edges_out(hipStream_t st, const float* D, int H, int W, float* E, float* A);
