@@ -45,3 +45,22 @@ def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_roofline_kernel_names_match_the_profiles():
+    """The roofline's kernel name is the one the rocprofv3 summaries are keyed
+    by (template instantiation included), and its source file is the one that
+    defines it, so the traffic lookup can find the counters."""
+    sys.path.insert(0, ROOT)
+    import json
+    import bench
+    assert bench.scan_kernels([50, 70] * 4) == ["k_scanlines<2>"]   # n = 51, 71
+    assert bench.scan_kernels([32]) == ["k_scanlines<2>"]           # n = 33
+    assert bench.scan_kernels([200, 400]) == ["k_scanlines<4>", "k_scanlines<8>"]
+    assert bench.scan_kernels([1023]) == ["k_scanlines<16>"]
+    keys = set(json.load(open(os.path.join(ROOT, "profiles", "traffic.json"))))
+    assert {"k_scanlines<2>", "k_edges"} <= keys
+    for k in keys - {"copy_probe"}:
+        base = k.split("<")[0]
+        src = open(os.path.join(ROOT, bench.kernel_source(k))).read()
+        assert f"void {base}(" in src or f"void {base}\n" in src or f" {base}(" in src, (k, bench.kernel_source(k))
