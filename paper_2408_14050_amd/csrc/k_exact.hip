@@ -618,6 +618,15 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
 template <int KMAX>
 constexpr int waves_per_block() { return KMAX >= 16 ? 2 : 4; }
 
+// The short-scanline forms (LDS allows 8 blocks of 4 wavefronts per CU) are
+// held to the hardware's 8 wavefronts per SIMD: the compiler then keeps to 96
+// scalar registers, spilling a few more into VGPR lanes.  The pass is bound
+// by chains of dependent loads (gather, LDS exchanges, merge searches), so
+// the extra wavefronts pay: c1 scanline pass 31.0 -> 26.6 us.  The longer
+// forms are limited by LDS below 8 anyway.
+template <int KMAX>
+constexpr int min_waves_per_simd() { return KMAX <= 2 ? 8 : 1; }
+
 constexpr int kGroup = 4;  // consecutive work items per wavefront visit
 
 // The batched kernel's prologue (a prefix over up to 1024 frames) is paid per
@@ -662,7 +671,7 @@ __device__ __forceinline__ void segment_of(const FrameDesc& f, int cls, int lo, 
 // One frame, the views of scan class cls: a flat walk over every
 // (view, candidate) pair of the class.
 template <int KMAX>
-__global__ __launch_bounds__(64 * waves_per_block<KMAX>()) void k_scanlines(
+__global__ __launch_bounds__(64 * waves_per_block<KMAX>(), min_waves_per_simd<KMAX>()) void k_scanlines(
     FrameDesc f, int n_views, ViewTable vt, Thresholds th, int cls) {
     constexpr int WPB = waves_per_block<KMAX>();
     constexpr int NT = 64 * WPB;
@@ -714,7 +723,7 @@ __global__ __launch_bounds__(64 * waves_per_block<KMAX>()) void k_scanlines(
 // is frame-major; frame sizes come from each frame's prefix, segments are
 // located in the frame's prefix in global memory.
 template <int KMAX>
-__global__ __launch_bounds__(64 * batched_waves_per_block<KMAX>()) void k_scanlines_batched(
+__global__ __launch_bounds__(64 * batched_waves_per_block<KMAX>(), min_waves_per_simd<KMAX>()) void k_scanlines_batched(
     const FrameDesc* __restrict__ table, int n_frames, int n_views, ViewTable vt, Thresholds th,
     int cls) {
     constexpr int WPB = batched_waves_per_block<KMAX>();
