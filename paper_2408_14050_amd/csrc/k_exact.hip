@@ -531,36 +531,59 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
         int mmax = 1;
         for (int rr = 0; rr < R; ++rr) mmax = max(mmax, L.rs[rr + 1] - L.rs[rr]);
         const int top = 31 - __clz(mmax);
+        int e_[K], own_[K], pos_[K];
+        uint32_t oe_[K];
         before = 0;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int e0 = k * 64 + lane;
             const bool valid = (vmask[k] >> lane) & 1ull;
-            const int e = valid ? e0 : e_lo;  // dropped lanes ride on a kept sample
+            e_[k] = valid ? e0 : e_lo;  // dropped lanes ride on a kept sample
             const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
-            const int own = valid ? before + __popcll(dm[k] & le) : 0;
+            own_[k] = valid ? before + __popcll(dm[k] & le) : 0;
             before += __popcll(dm[k]);
-            const float We = wk[k];
-            const uint32_t oe = f2ord(We);
-            int pos = e - L.rs[own];
+            oe_[k] = f2ord(wk[k]);
+            pos_[k] = e_[k] - L.rs[own_[k]];
+        }
+        // The searches of up to KC samples of a lane advance in lockstep, so
+        // their dependent LDS reads overlap instead of queueing one after
+        // the other.
+        constexpr int KC = K < 4 ? K : 4;
+#pragma unroll
+        for (int k0 = 0; k0 < K; k0 += KC) {
             for (int i = 0; i + 1 < R; ++i) {
-                const int rr = i < own ? i : i + 1;
-                // keys of run rr below (W_e, e): O_j < ord(W_e), or <= for a run
-                // before e (equal W precede e); branch-free lower bound
-                const uint32_t T = oe + (rr < own ? 1u : 0u);
-                const int s0 = L.rs[rr];
-                int base = s0, len = L.rs[rr + 1] - s0;
-                for (int st = top; st >= 0; --st) {
-                    const int half = len >> 1;
-                    base = (L.Oin[base + half] < T) ? base + half : base;
-                    len -= half;
+                uint32_t T[KC];
+                int s0[KC], base[KC], len[KC];
+#pragma unroll
+                for (int j = 0; j < KC; ++j) {
+                    const int own = own_[k0 + j];
+                    const int rr = i < own ? i : i + 1;
+                    // keys of run rr below (W_e, e): O_j < ord(W_e), or <= for
+                    // a run before e (equal W precede e); branch-free lower bound
+                    T[j] = oe_[k0 + j] + (rr < own ? 1u : 0u);
+                    s0[j] = L.rs[rr];
+                    base[j] = s0[j];
+                    len[j] = L.rs[rr + 1] - s0[j];
                 }
-                pos += base - s0 + ((L.Oin[base] < T) ? 1 : 0);
+                for (int st = top; st >= 0; --st) {
+#pragma unroll
+                    for (int j = 0; j < KC; ++j) {
+                        const int half = len[j] >> 1;
+                        base[j] = (L.Oin[base[j] + half] < T[j]) ? base[j] + half : base[j];
+                        len[j] -= half;
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < KC; ++j)
+                    pos_[k0 + j] += base[j] - s0[j] + ((L.Oin[base[j]] < T[j]) ? 1 : 0);
             }
-            pk[k] = pos;
-            if (valid) {
-                L.Ws[pos] = We;
-                L.Vs[pos] = L.Vin[e];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            pk[k] = pos_[k];
+            if ((vmask[k] >> lane) & 1ull) {
+                L.Ws[pos_[k]] = wk[k];
+                L.Vs[pos_[k]] = L.Vin[e_[k]];
             }
         }
         Ws = L.Ws;
