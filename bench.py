@@ -144,12 +144,16 @@ def cpu_baseline(sc, seconds: float):
 # ---------------------------------------------------------------------------
 PROFILE_CMD = ("rocprofv3 {mode} -d gpurun_out/{out} -o run -- python3 bench.py --steps 20 "
                "--warmup 2 --prewarm 0 --streams 1 --no-cpu-baseline --no-context --no-check "
-               "--no-learned")
+               "--no-learned --no-quality")
+QUALITY_PROFILE_CMD = ("rocprofv3 {mode} -d gpurun_out/{out} -o run -- python3 bench.py "
+                       "--quality-only")
 LEARNED_PROFILE_CMD = ("rocprofv3 {mode} -d gpurun_out/{out} -o run -- python3 bench.py --learned-only "
                        "--learned-steps 10 --learned-eval 1")
 BATCH_WORKLOAD = "c3 64 mixed frames seed 3000"
+QUALITY_WORKLOAD = "c1 1280x960 x8 views seeds 1000-1003"
 LEARNED_WORKLOAD = "c4 1920x1080 x8 views seed 4100"
 LEARNED_KERNELS = ("k_pack", "k_conv", "k_route")
+QUALITY_KERNELS = ("k_zbuf", "k_fill", "k_median", "k_confusion", "k_stats")
 COPY_CMD = "rocprofv3 --pmc {ctr} -d gpurun_out/{out} -o run -- python3 bench.py --copy-probe 256"
 
 
@@ -188,13 +192,16 @@ def _trace_per_kernel(db_path: str):
     tab = "kernels" if "kernels" in tabs else [t for t in tabs if t.startswith("rocpd_kernel_dispatch")][0]
     cols = [r[1] for r in con.execute(f"pragma table_info({tab})")]
     name_col = "name" if "name" in cols else "kernel_name"
-    rows = con.execute(f"select {name_col}, start, end from {tab}").fetchall()
-    out = {}
-    for name, st, en in rows:
+    grid = "grid_x" if "grid_x" in cols else None
+    rows = con.execute(f"select {name_col}, start, end, {grid or 0} from {tab}").fetchall()
+    out, by_grid = {}, {}
+    for name, st, en, gx in rows:
         m = re.search(r"(k_[a-z_0-9]+(<[0-9, ]+>)?)", name or "")
         key = m.group(1) if m else (name or "?").split("(")[0][-40:]
         out.setdefault(key, []).append((en - st) / 1e3)
-    return {k: {"calls": len(v), "avg_us": sum(v) / len(v), "min_us": min(v), "max_us": max(v)}
+        by_grid.setdefault(key, {}).setdefault(int(gx or 0), []).append((en - st) / 1e3)
+    return {k: {"calls": len(v), "avg_us": sum(v) / len(v), "min_us": min(v), "max_us": max(v),
+                "by_grid": {g: (len(d), sum(d) / len(d)) for g, d in sorted(by_grid[k].items())}}
             for k, v in out.items()}
 
 
@@ -217,8 +224,9 @@ def profiles_from(run_dir: str, workload: str) -> int:
                               "write_kib": max(cw.values()) if cw else None,
                               "read_factor": f_read, "write_factor": f_write}}
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
-    runs = [("", PROFILE_CMD, lambda k: not k.startswith(LEARNED_KERNELS)),
-            ("l", LEARNED_PROFILE_CMD, lambda k: k.startswith(LEARNED_KERNELS))]
+    runs = [("", PROFILE_CMD, lambda k: not k.startswith(LEARNED_KERNELS + QUALITY_KERNELS)),
+            ("l", LEARNED_PROFILE_CMD, lambda k: k.startswith(LEARNED_KERNELS)),
+            ("q", QUALITY_PROFILE_CMD, lambda k: k.startswith(QUALITY_KERNELS))]
     for pre, cmd, keep in runs:
         if not db(pre + "prof"):
             continue
@@ -226,8 +234,10 @@ def profiles_from(run_dir: str, workload: str) -> int:
         fetch = _pmc_per_kernel(db(pre + "pmc_fetch"), "FETCH_SIZE")
         write = _pmc_per_kernel(db(pre + "pmc_write"), "WRITE_SIZE")
         for k in sorted(k for k in set(trace) & set(fetch) & set(write) if k.startswith("k_") and keep(k)):
-            if pre:
+            if pre == "l":
                 wl = LEARNED_WORKLOAD
+            elif pre == "q":
+                wl = QUALITY_WORKLOAD
             else:
                 wl = BATCH_WORKLOAD if "batched" in k else workload
             tag = wl.split(":")[0].replace(" ", "_").replace("x8_views", "v8")
@@ -252,6 +262,8 @@ def profiles_from(run_dir: str, workload: str) -> int:
                 f"dispatches: {trace[k]['calls']}",
                 f"duration avg/min/max (us): {trace[k]['avg_us']:.2f} / {trace[k]['min_us']:.2f} / "
                 f"{trace[k]['max_us']:.2f}",
+                "by grid size (work-items: dispatches, avg us; the autotuner's trial shapes included):",
+            ] + [f"  {g}: {c}, {a:.2f}" for g, (c, a) in trace[k]["by_grid"].items()] + [
                 f"FETCH_SIZE per dispatch (KiB): {fetch[k]:.1f}",
                 f"WRITE_SIZE per dispatch (KiB): {write[k]:.1f}",
                 f"copy probe 256 MiB: FETCH_SIZE {traffic['copy_probe']['fetch_kib']} KiB, "
@@ -495,6 +507,7 @@ def main() -> int:
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-only", action="store_true", help="only the learned-path section")
     ap.add_argument("--no-quality", action="store_true")
+    ap.add_argument("--quality-only", action="store_true", help="only the quality and fusion sections")
     ap.add_argument("--streams", type=int, default=3,
                     help="frames in flight: contexts on separate HIP streams, steps round-robin")
     ap.add_argument("--prewarm", type=int, default=PREWARM_STEPS,
@@ -522,6 +535,12 @@ def main() -> int:
     if args.learned_only:
         ctx = occl.Context(0)
         print(json.dumps(bench_learned(ctx, args.learned_steps, args.learned_eval)), flush=True)
+        ctx.occl_release()
+        return 0
+    if args.quality_only:
+        ctx = occl.Context(0)
+        print(json.dumps({"quality_vs_zbuffer": bench_quality(ctx), "median_fusion": bench_fusion(ctx)}),
+              flush=True)
         ctx.occl_release()
         return 0
     sc = scenes.make_scene("c1", args.seed)
@@ -597,19 +616,23 @@ def main() -> int:
     n_cand = ctx.occl_last_candidate_counts(V)
     edge_ms = prof["edges"][0] / max(1, prof["edges"][1])
     scan_ms = prof["scanlines"][0] / max(1, prof["scanlines"][1])
+    # the scanline pass alone, re-run back to back between two events on its
+    # stream (an event pair around each single launch adds the dispatch gap)
+    scan_ms_rep = ctx.occl_time_scanlines(args.steps)
 
     workload = f"c1 {W}x{H} x{V} views seed {args.seed}"
     alg_bytes = (4 + V) * H * W                       # D read once + every mask byte written once
     path_gbps = alg_bytes / (ms_per_step * 1e-3) / 1e9
     if scan_ms >= edge_ms:
         ops = scanline_ops(n_cand, sc.scan_len, sc.params["neighbours"])
-        achieved = ops / (scan_ms * 1e-3) / 1e9
+        achieved = ops / (scan_ms_rep * 1e-3) / 1e9
         ks = scan_kernels(sc.scan_len)  # one launch per class; c1 has one
         roof = {"kernel": ks[0] if len(ks) == 1 else "k_scanlines", "bound": "alu",
                 "achieved": round(achieved, 2), "peak": ALU_PEAK_GOPS, "unit": "Gop/s",
                 "frac": round(achieved / ALU_PEAK_GOPS, 5),
                 "traffic": traffic_for(ks[0], workload) if len(ks) == 1 else None,
-                "avg_ms": round(scan_ms, 5), "ops_per_launch": ops}
+                "avg_ms": round(scan_ms_rep, 5), "avg_ms_event_pair_per_step": round(scan_ms, 5),
+                "ops_per_launch": ops}
     else:
         achieved = alg_bytes / (edge_ms * 1e-3) / 1e9
         roof = {"kernel": "k_edges", "bound": "hbm", "achieved": round(achieved, 1),

@@ -308,6 +308,16 @@ occl_status occl_profile_enable(occl_ctx* ctx, int32_t enable);
 occl_status occl_profile_read(occl_ctx* ctx, double* ms /* [OCCL_N_STAGES] */,
                               int64_t* launches /* [OCCL_N_STAGES] */);
 
+/* Measurement of the scanline pass alone: re-enqueues the scanline launches of
+ * the context's most recent exact-path frame `reps` times back to back between
+ * two HIP events on the context's stream, synchronises, and returns the mean
+ * milliseconds per pass (Eqs. (4)-(6), one launch per register class present).
+ * The pass only sets mask bytes that the first pass already set, so the masks
+ * do not change.  D and M of that call must still be valid (call it right
+ * after occl_detect).  OCCL_ERR_STATE when there is no such frame or the
+ * context's list workspace has been reallocated since. */
+occl_status occl_time_scanlines(occl_ctx* ctx, int32_t reps, double* ms_per_pass);
+
 const char* occl_status_string(occl_status s);
 const char* occl_last_error(const occl_ctx* ctx);
 

@@ -451,6 +451,43 @@ occl_status occl_ctx::enqueue_frame(const float* D, int H, int W, int n_views, c
     prof_end(OCCL_STAGE_SCANLINES, ev);
     last_frame = f;
     last_views = n_views;
+    last_vt = vt;
+    last_th = th;
+    last_scan_grid = tc.scan_blocks_per_cu * n_cu;
+    return OCCL_OK;
+}
+
+extern "C" occl_status occl_time_scanlines(occl_ctx* ctx, int32_t reps, double* ms_per_pass) {
+    if (!ctx || !ms_per_pass || reps < 1) return OCCL_ERR_INVALID_ARG;
+    (void)hipSetDevice(ctx->device);
+    const FrameDesc& f = ctx->last_frame;
+    // the lists and prefix must still be the ones that call wrote
+    auto li = ctx->bufs.find("lists");
+    auto pr = ctx->bufs.find("prefix");
+    if (ctx->last_views <= 0 || li == ctx->bufs.end() || pr == ctx->bufs.end() ||
+        li->second.ptr != (void*)f.lists || pr->second.ptr != (void*)f.prefix)
+        return ctx->fail(OCCL_ERR_STATE, "no exact-path frame to re-time");
+    hipEvent_t a = ctx->take_event(), b = ctx->take_event();
+    if (!a || !b) {
+        if (a) ctx->ev_pool.push_back(a);
+        if (b) ctx->ev_pool.push_back(b);
+        return ctx->fail(OCCL_ERR_HIP, "hipEventCreate(time_scanlines)");
+    }
+    hipError_t e = hipEventRecord(a, ctx->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r)
+        for (int ci = 0; ci < kNumClasses && e == hipSuccess; ++ci) {
+            if (f.cls_start[ci + 1] == f.cls_start[ci]) continue;
+            e = launch_scanlines(ctx->stream, f, ctx->last_views, ctx->last_vt, ctx->last_th, ci,
+                                 ctx->last_scan_grid);
+        }
+    if (e == hipSuccess) e = hipEventRecord(b, ctx->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    ctx->ev_pool.push_back(a);
+    ctx->ev_pool.push_back(b);
+    if (e != hipSuccess) return ctx->hip_fail(e, "time_scanlines");
+    *ms_per_pass = (double)ms / reps;
     return OCCL_OK;
 }
 

@@ -36,6 +36,9 @@ struct occl_ctx {
     std::string last_error;
     int last_views = 0;
     occl::FrameDesc last_frame{};        // layout of the most recent single-frame call
+    occl::ViewTable last_vt{};           // its views, thresholds and scanline grid
+    occl::Thresholds last_th{};
+    int last_scan_grid = 0;
 
     // launch shapes: tuned per bucket (tune_key), default otherwise
     std::map<uint64_t, occl::TuneConfig> tuned;

@@ -88,6 +88,7 @@ _SIGS = {
     "occl_direction": (C.c_int, [C.c_double, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
     "occl_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "occl_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "occl_time_scanlines": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
     "occl_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
                                 C.POINTER(C.c_double), C.POINTER(C.c_float), C.POINTER(occl_params),
                                 C.c_void_p, C.c_int32, C.POINTER(occl_tune)]),
@@ -350,6 +351,13 @@ class Context:
                                      n.ctypes.data_as(C.POINTER(C.c_int64)))
         self._check(st, "occl_profile_read")
         return {s: (float(ms[i]), int(n[i])) for i, s in enumerate(STAGES)}
+
+    def occl_time_scanlines(self, reps: int = 100):
+        """Mean ms per scanline pass of the last occl_detect, re-run `reps`
+        times back to back (synchronises; the masks do not change)."""
+        ms = C.c_double()
+        self._check(lib().occl_time_scanlines(self.h, int(reps), C.byref(ms)), "occl_time_scanlines")
+        return ms.value
 
     def occl_detect_routed(self, D, angles, ratios, prm: occl_params, logits, M=None,
                            tile_state=None):

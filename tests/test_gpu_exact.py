@@ -377,3 +377,22 @@ def test_prepared_call_and_frames_in_flight(torch, ref):
         assert_parity(M.cpu().numpy(), M_ref, None, "frames in flight")
     for c in ctxs:
         c.occl_release()
+
+
+def test_time_scanlines_leaves_masks_unchanged(gctx, torch, ref):
+    """The measurement entry point re-runs the last frame's scanline pass: the
+    masks stay those of the oracle, and without an exact-path frame the call
+    is refused."""
+    from paper_2408_14050_amd import occl
+    ctx = occl.Context(0)
+    with pytest.raises(occl.OcclError):
+        ctx.occl_time_scanlines(3)
+    sc = scenes.make_scene("c0", 7)
+    D = torch.from_numpy(np.ascontiguousarray(sc.D)).cuda()
+    prm = occl.params(scan_len_per_view=sc.scan_len, **sc.params)
+    M = ctx.occl_detect(D, sc.angles, sc.ratios, prm)
+    ms = ctx.occl_time_scanlines(20)
+    assert 0.0 < ms < 100.0
+    M_ref, _, _ = ref.detect(sc.D, sc.angles, sc.ratios, sc.scan_len, **sc.params)
+    assert_parity(M.cpu().numpy(), M_ref, None, "after re-timed scanline passes")
+    ctx.occl_release()
