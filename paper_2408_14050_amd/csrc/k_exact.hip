@@ -578,12 +578,16 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
                     pos_[k0 + j] += base[j] - s0[j] + ((L.Oin[base[j]] < T[j]) ? 1 : 0);
             }
         }
+        // every read of Vin before the first write: Vs may share Vin's storage
+        float vv[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) vv[k] = L.Vin[e_[k]];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             pk[k] = pos_[k];
             if ((vmask[k] >> lane) & 1ull) {
                 L.Ws[pos_[k]] = wk[k];
-                L.Vs[pos_[k]] = L.Vin[e_[k]];
+                L.Vs[pos_[k]] = vv[k];
             }
         }
         Ws = L.Ws;
@@ -599,20 +603,26 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
         }
         bitonic_sort<K>(key, lane);
         // the sorted array holds the origin of position p in key[k]; scatter the
-        // inverse (origin -> position) so the test below runs per kept sample
+        // inverse (origin -> position) into the key array, unused on this
+        // path, so the test below runs per kept sample.  Every read of Vin
+        // comes before the first write (Vs may share Vin's storage).
+        float vv[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) vv[k] = L.Vin[(k * 64 + lane < nvalid) ? (uint32_t)key[k] : 0u];
+        int* inv = reinterpret_cast<int*>(L.Oin);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int p = k * 64 + lane;
             if (p < nvalid) {
                 const uint32_t o = (uint32_t)key[k];
                 L.Ws[p] = ord2f((uint32_t)(key[k] >> 32));
-                L.Vs[p] = L.Vin[o];
-                reinterpret_cast<int*>(L.Win)[o] = p;  // Win is free again: origin -> position
+                L.Vs[p] = vv[k];
+                inv[o] = p;
             }
         }
         wave_lds_sync();
 #pragma unroll
-        for (int k = 0; k < K; ++k) pk[k] = reinterpret_cast<const int*>(L.Win)[min(k * 64 + lane, N - 1)];
+        for (int k = 0; k < K; ++k) pk[k] = inv[min(k * 64 + lane, N - 1)];
         Ws = L.Ws;
         Vs = L.Vs;
         wave_lds_sync();
@@ -649,6 +659,14 @@ constexpr int waves_per_block() { return KMAX >= 16 ? 2 : 4; }
 // forms are limited by LDS below 8 anyway.
 template <int KMAX>
 constexpr int min_waves_per_simd() { return KMAX <= 2 ? 8 : 1; }
+
+// Float arrays per wavefront in LDS: Vin, Win, and the sorted Vs, Ws.  The
+// long-scanline forms are limited by LDS, so their sorted arrays share the
+// input arrays' storage (every path reads what it needs of the inputs before
+// writing the sorted values); c2 (K = 8) then fits 4 blocks per CU instead
+// of 3.
+template <int KMAX>
+constexpr int lds_arrays() { return KMAX >= 4 ? 2 : 4; }
 
 constexpr int kGroup = 4;  // consecutive work items per wavefront visit
 
@@ -698,7 +716,7 @@ __global__ __launch_bounds__(64 * waves_per_block<KMAX>(), min_waves_per_simd<KM
     FrameDesc f, int n_views, ViewTable vt, Thresholds th, int cls) {
     constexpr int WPB = waves_per_block<KMAX>();
     constexpr int NT = 64 * WPB;
-    __shared__ float lds[WPB][4][64 * KMAX];
+    __shared__ float lds[WPB][lds_arrays<KMAX>()][64 * KMAX];
     __shared__ uint32_t okeys[WPB][64 * KMAX];
     __shared__ int runs[WPB][kMaxRunsCap + 1];
     __shared__ int pre[kMaxSegments + 1];
@@ -718,7 +736,8 @@ __global__ __launch_bounds__(64 * waves_per_block<KMAX>(), min_waves_per_simd<KM
     const int total = pre[nseg];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const WaveLds L{lds[wave][0], lds[wave][1], okeys[wave], lds[wave][2], lds[wave][3], runs[wave]};
+    constexpr int NA = lds_arrays<KMAX>();
+    const WaveLds L{lds[wave][0], lds[wave][1], okeys[wave], lds[wave][NA - 2], lds[wave][NA - 1], runs[wave]};
     // Blocked round-robin: wavefront gw takes groups of kGroup consecutive
     // items at gw*kGroup, gw*kGroup + nw*kGroup, ...  All wavefronts sweep the
     // list together (a small live working set of D), and within a group the
@@ -751,7 +770,7 @@ __global__ __launch_bounds__(64 * batched_waves_per_block<KMAX>(), min_waves_per
     int cls) {
     constexpr int WPB = batched_waves_per_block<KMAX>();
     constexpr int NT = 64 * WPB;
-    __shared__ float lds[WPB][4][64 * KMAX];
+    __shared__ float lds[WPB][lds_arrays<KMAX>()][64 * KMAX];
     __shared__ uint32_t okeys[WPB][64 * KMAX];
     __shared__ int runs[WPB][kMaxRunsCap + 1];
     __shared__ int fpre[kMaxBatch + 1];
@@ -796,7 +815,8 @@ __global__ __launch_bounds__(64 * batched_waves_per_block<KMAX>(), min_waves_per
     const int total = fpre[n_frames];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const WaveLds L{lds[wave][0], lds[wave][1], okeys[wave], lds[wave][2], lds[wave][3], runs[wave]};
+    constexpr int NA = lds_arrays<KMAX>();
+    const WaveLds L{lds[wave][0], lds[wave][1], okeys[wave], lds[wave][NA - 2], lds[wave][NA - 1], runs[wave]};
     // blocked round-robin over the frame-major list (see k_scanlines): all
     // wavefronts work on neighbouring frames at any time
     const int nw = gridDim.x * WPB;
