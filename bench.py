@@ -282,11 +282,12 @@ def profiles_from(run_dir: str, workload: str) -> int:
 
 def tune_in_flight(ctxs, run, reps: int = 200):
     """Launch shape for frames in flight, chosen by measured throughput (not
-    timed).  The autotuner picks the scanline grid that finishes one frame
-    soonest; with several frames in flight a grid that leaves a wavefront slot
-    per SIMD to the next frame's edge pass can move more frames.  Tries the
-    autotuned blocks per CU and a few below it on every context, keeps the
-    fastest and returns it."""
+    timed).  The autotuner picks the shape that finishes one frame soonest;
+    with several frames in flight a scanline grid that leaves a wavefront
+    slot per SIMD to the next frame's edge pass, or another edge-pass block
+    height, can move more frames.  Tries the autotuned blocks per CU and a few
+    below it, then edge-pass heights around the autotuned one, on every
+    context; keeps the fastest and returns it."""
     import tempfile
     import torch
     path = os.path.join(tempfile.gettempdir(), f"occl_tune_{os.getpid()}.txt")
@@ -294,11 +295,10 @@ def tune_in_flight(ctxs, run, reps: int = 200):
     rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
     if not rows:
         return None
-    bpc0 = int(rows[0][2])
-    best = None
-    for bpc in sorted({bpc0, max(1, bpc0 - 1), max(1, bpc0 - 2), 2 * bpc0}):
+
+    def timed(er, bpc):
         with open(path, "w") as f:
-            for key, er, _ in rows:
+            for key, _, _ in rows:
                 f.write(f"{key} {er} {bpc}\n")
         for c in ctxs:
             c.occl_tune_load(path)
@@ -307,16 +307,17 @@ def tune_in_flight(ctxs, run, reps: int = 200):
         t0 = time.perf_counter()
         run(reps)
         torch.cuda.synchronize()
-        us = (time.perf_counter() - t0) / reps * 1e6
-        if best is None or us < best[1]:
-            best = (bpc, us)
-    with open(path, "w") as f:
-        for key, er, _ in rows:
-            f.write(f"{key} {er} {best[0]}\n")
-    for c in ctxs:
-        c.occl_tune_load(path)
+        return (time.perf_counter() - t0) / reps * 1e6
+
+    er0, bpc0 = int(rows[0][1]), int(rows[0][2])
+    best = min(((timed(er0, b), er0, b) for b in sorted({bpc0, max(1, bpc0 - 1), max(1, bpc0 - 2),
+                                                         2 * bpc0})), key=lambda t: t[0])
+    for er in sorted({max(1, er0 // 2), min(16, er0 * 2)} - {er0}):
+        t = (timed(er, best[2]), er, best[2])
+        best = min(best, t, key=lambda t: t[0])
+    timed(best[1], best[2])  # leave the winner loaded
     os.remove(path)
-    return {"edge_rows": int(rows[0][1]), "scan_blocks_per_cu": best[0]}
+    return {"edge_rows": best[1], "scan_blocks_per_cu": best[2]}
 
 
 def bench_batched(ctx, steps: int, tune: bool):
