@@ -101,7 +101,7 @@ occl_status occl_ctx::enqueue_batch(int n_frames, const occl_frame* frames, int 
     sg.total_blocks = total_blocks;
     sg.n_views = n_views;
     sg.edge_rows = tc.edge_rows;
-    sg.edge_grid = std::min(total_blocks, n_cu * std::max(1, 32 / tc.edge_rows));
+    sg.edge_grid = std::min(total_blocks, n_cu * edges_batched_blocks_per_cu(tc.edge_rows));
     sg.scan_grid = tc.scan_blocks_per_cu * n_cu;
     sg.cls_mask = cls_mask;
     sg.th = th;

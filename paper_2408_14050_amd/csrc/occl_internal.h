@@ -127,6 +127,9 @@ hipError_t launch_edges(hipStream_t st, const FrameDesc& f, int n_views, const V
                         float q_min);
 hipError_t launch_scanlines(hipStream_t st, const FrameDesc& f, int n_views, const ViewTable& vt,
                             const Thresholds& th, int cls, int n_blocks);
+// Resident blocks per CU of the batched edge pass at this block height (its
+// persistent grid must not exceed what fits at once).
+int edges_batched_blocks_per_cu(int edge_rows);
 hipError_t launch_edges_batched(hipStream_t st, const FrameDesc* table, int n_frames,
                                 int total_blocks, int n_views, const ViewTable& vt, float q_min,
                                 int edge_rows, int n_blocks);
