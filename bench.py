@@ -52,16 +52,17 @@ def kernel_hash(kernel: str = "k_scanlines") -> str:
 
 
 def scan_kernels(scan_len):
-    """Names of the scanline-pass kernels a frame launches: one per register
-    class of its views (K = 2, 4, 8, 16 samples per lane for n = 2h + 1
-    samples, K <= 2 sharing the first)."""
+    """Names of the scanline-pass kernels a plain exact-path frame launches:
+    one per register class of its views (K = 2, 4, 8, 16 samples per lane for
+    n = 2h + 1 samples, K <= 2 sharing the first); the second template
+    argument 0 is the form without the bilinear / routed-tile checks."""
     out = []
     for L in scan_len:
         n = 2 * (int(L) // 2) + 1
         K = 1
         while 64 * K < n:
             K *= 2
-        name = f"k_scanlines<{max(K, 2)}>"
+        name = f"k_scanlines<{max(K, 2)}, 0>"
         if name not in out:
             out.append(name)
     return out

@@ -54,12 +54,12 @@ def test_roofline_kernel_names_match_the_profiles():
     sys.path.insert(0, ROOT)
     import json
     import bench
-    assert bench.scan_kernels([50, 70] * 4) == ["k_scanlines<2>"]   # n = 51, 71
-    assert bench.scan_kernels([32]) == ["k_scanlines<2>"]           # n = 33
-    assert bench.scan_kernels([200, 400]) == ["k_scanlines<4>", "k_scanlines<8>"]
-    assert bench.scan_kernels([1023]) == ["k_scanlines<16>"]
+    assert bench.scan_kernels([50, 70] * 4) == ["k_scanlines<2, 0>"]   # n = 51, 71
+    assert bench.scan_kernels([32]) == ["k_scanlines<2, 0>"]           # n = 33
+    assert bench.scan_kernels([200, 400]) == ["k_scanlines<4, 0>", "k_scanlines<8, 0>"]
+    assert bench.scan_kernels([1023]) == ["k_scanlines<16, 0>"]
     keys = set(json.load(open(os.path.join(ROOT, "profiles", "traffic.json"))))
-    assert {"k_scanlines<2>", "k_edges"} <= keys
+    assert {"k_scanlines<2, 0>", "k_edges"} <= keys
     for k in keys - {"copy_probe"}:
         base = k.split("<")[0]
         src = open(os.path.join(ROOT, bench.kernel_source(k))).read()
