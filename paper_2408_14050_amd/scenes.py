@@ -246,6 +246,29 @@ def _c0(seed: int) -> Scene:
                  np.array([32], dtype=np.int32), dict(PARAMS_C0))
 
 
+def extent_scene(H: int, W: int, seed: int) -> Scene:
+    """A thin frame at an extreme extent (for example 24 x 65535): a gentle
+    ramp (no edges above gamma) with 400 constant rectangles of disparity
+    8..40 and a band of disparity 30 along the far edge of the long side, so
+    that candidates reach the largest coordinates; 8 views at 45 degree steps,
+    ratios 1 / sqrt(2) alternating, L = 50 / 70."""
+    rng = np.random.default_rng(seed)
+    yy, xx = np.mgrid[0:H, 0:W]
+    D = (4.0 + 0.01 * (xx % 97) + 0.01 * (yy % 89)).astype(np.float32)
+    for _ in range(400):
+        h, w = int(rng.integers(2, min(H, 40) + 1)), int(rng.integers(2, min(W, 40) + 1))
+        y0, x0 = int(rng.integers(0, H - h + 1)), int(rng.integers(0, W - w + 1))
+        D[y0:y0 + h, x0:x0 + w] = np.float32(rng.uniform(8.0, 40.0))
+    if W >= H:
+        D[:, -5:] = np.float32(30.0)
+    if H >= W:
+        D[-5:, :] = np.float32(30.0)
+    angles = np.arange(8) * 45.0
+    ratios = np.where(np.arange(8) % 2 == 1, np.float32(np.sqrt(2.0)), np.float32(1.0)).astype(np.float32)
+    return Scene(f"extent{H}x{W}", seed, np.ascontiguousarray(D), angles, ratios,
+                 np.array([50, 70] * 4, np.int32))
+
+
 def make_c1_like(seed_or_rng, W: int = 1280, H: int = 960, n_objects: int = 20,
                  dmax: float = 48.0, noise: float = 0.1, name: str = "c1", seed: int = -1) -> Scene:
     """c1 statistics at any frame size (object sizes scale with W / 1280)."""

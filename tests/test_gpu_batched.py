@@ -146,3 +146,14 @@ def test_autotune_and_tune_file(gctx, torch, ref, tmp_path):
     assert bb["ms"] > 0
     for f, M_ in zip(frames, Ms):
         assert np.array_equal(M_.cpu().numpy(), _ref(ref, f))
+
+
+def test_extreme_extents_in_one_batch(gctx, torch, ref):
+    """Frames 65535 wide and 65535 tall batched with a small one (same views):
+    every mask equals the oracle's."""
+    frames = [scenes.extent_scene(24, 65535, 70024), scenes.extent_scene(65535, 24, 70035),
+              scenes.extent_scene(40, 300, 70040)]
+    _, Ms = _run_batch(gctx, torch, frames)
+    for f, M in zip(frames, Ms):
+        np.testing.assert_array_equal(M.cpu().numpy(), _ref(ref, f), err_msg=f.name)
+

@@ -403,21 +403,9 @@ def test_maximum_frame_extent(gctx, torch, ref, shape):
     """The largest accepted width and height (candidate coordinates packed
     into 16 bits each reach 65534): bit-exact with the oracle."""
     H, W = shape
-    rng = np.random.default_rng(70000 + H)
-    yy, xx = np.mgrid[0:H, 0:W]
-    D = (4.0 + 0.01 * (xx % 97) + 0.01 * (yy % 89)).astype(np.float32)
-    for _ in range(400):
-        h, w = int(rng.integers(2, min(H, 40) + 1)), int(rng.integers(2, min(W, 40) + 1))
-        y0, x0 = int(rng.integers(0, H - h + 1)), int(rng.integers(0, W - w + 1))
-        D[y0:y0 + h, x0:x0 + w] = np.float32(rng.uniform(8.0, 40.0))
-    # occluders touching the far edges, where x or y reaches 65534
-    D[:, -5:] = np.float32(30.0) if W > H else D[:, -5:]
-    D[-5:, :] = np.float32(30.0) if H > W else D[-5:, :]
-    angles = np.arange(8) * 45.0
-    ratios = np.where(np.arange(8) % 2 == 1, np.float32(np.sqrt(2.0)), np.float32(1.0)).astype(np.float32)
-    L = np.array([50, 70] * 4, np.int32)
-    M_ref, _, nc_ref = ref.detect(D, angles, ratios, L)
-    M, nc = run_gpu(gctx, torch, D, angles, ratios, L, counts=True)
+    sc = scenes.extent_scene(H, W, 70000 + H)
+    M_ref, _, nc_ref = ref.detect(sc.D, sc.angles, sc.ratios, sc.scan_len)
+    M, nc = run_gpu(gctx, torch, sc.D, sc.angles, sc.ratios, sc.scan_len, counts=True)
     np.testing.assert_array_equal(nc, nc_ref)
     assert nc.sum() > 0
     assert_parity(M, M_ref, None, f"{H}x{W}")
