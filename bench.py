@@ -637,9 +637,9 @@ def main() -> int:
                 "ops_per_launch": ops}
     else:
         achieved = alg_bytes / (edge_ms * 1e-3) / 1e9
-        roof = {"kernel": "k_edges", "bound": "hbm", "achieved": round(achieved, 1),
+        roof = {"kernel": "k_edges<0>", "bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                "traffic": traffic_for("k_edges", workload), "avg_ms": round(edge_ms, 5),
+                "traffic": traffic_for("k_edges<0>", workload), "avg_ms": round(edge_ms, 5),
                 "bytes_per_launch": alg_bytes}
 
     out = {

@@ -193,7 +193,9 @@ __device__ __forceinline__ EdgeIn edge_load(const FrameDesc& f, int bx, int by) 
     return in;
 }
 
-template <bool kFinish>
+// kRouted: the frame may carry tile states / a reach map (routed exact
+// fallback); 0 compiles those lookups out of the plain path.
+template <bool kFinish, int kRouted>
 __device__ void edge_block(const FrameDesc& f, int bx, int by, int n_views, const ViewTable& vt,
                            float q_min, const EdgeIn& in) {
     const int H = f.H, W = f.W;
@@ -232,7 +234,7 @@ __device__ void edge_block(const FrameDesc& f, int bx, int by, int n_views, cons
             for (int v = 0; v < n_views; ++v) {
                 uint8_t* mrow = f.M + v * HW + (size_t)y * W;
                 const uint8_t fill =
-                    f.tstate ? (f.tstate[((size_t)v * tiles_y + y / kTile) * f.tiles_x + x0 / kTile] == 1)
+                    (kRouted && f.tstate) ? (f.tstate[((size_t)v * tiles_y + y / kTile) * f.tiles_x + x0 / kTile] == 1)
                              : 0;
                 if (vec) {
                     *reinterpret_cast<uint32_t*>(mrow + x0) = 0x01010101u * fill;
@@ -264,7 +266,7 @@ __device__ void edge_block(const FrameDesc& f, int bx, int by, int n_views, cons
                     // routed frames keep only candidates that can reach an exact
                     // tile (x0 .. x0 + 3 share one tile)
                     const bool near =
-                        !f.tnear || (live && f.tnear[((size_t)v * ((H + kTile - 1) / kTile) + y / kTile) *
+                        !kRouted || !f.tnear || (live && f.tnear[((size_t)v * ((H + kTile - 1) / kTile) + y / kTile) *
                                                          f.tiles_x + x0 / kTile]);
                     uint64_t b[4];
 #pragma unroll
@@ -339,9 +341,10 @@ __device__ void edge_block(const FrameDesc& f, int bx, int by, int n_views, cons
     __syncthreads();
 }
 
+template <int kRouted>
 __global__ __launch_bounds__(64 * kMaxEdgeRows) void k_edges(FrameDesc f, int n_views, ViewTable vt,
                                                                float q_min) {
-    edge_block<true>(f, blockIdx.x, blockIdx.y, n_views, vt, q_min, edge_load(f, blockIdx.x, blockIdx.y));
+    edge_block<true, kRouted>(f, blockIdx.x, blockIdx.y, n_views, vt, q_min, edge_load(f, blockIdx.x, blockIdx.y));
 }
 
 // Every frame of a batch: a persistent grid walks the flat list of edge-pass
@@ -382,7 +385,7 @@ __global__ __launch_bounds__(64 * kMaxEdgeRows, 8) void k_edges_batched(
             nxt = edge_load(table[nfi], nlocal % table[nfi].gx, nlocal / table[nfi].gx);
         }
         const FrameDesc& f = table[fi];
-        edge_block<false>(f, local % f.gx, local / f.gx, n_views, vt, q_min, cur);
+        edge_block<false, 0>(f, local % f.gx, local / f.gx, n_views, vt, q_min, cur);  // never routed
         vb = nvb;
         fi = nfi;
         local = nlocal;
@@ -959,8 +962,12 @@ void describe_frame(FrameDesc* f, const float* D, uint8_t* M, int H, int W, int 
 
 hipError_t launch_edges(hipStream_t st, const FrameDesc& f, int n_views, const ViewTable& vt,
                         float q_min) {
-    hipLaunchKernelGGL(k_edges, dim3(f.gx, f.gy), dim3(64 * f.ll.edge_rows), 0, st, f, n_views, vt,
-                       q_min);
+    if (f.tstate || f.tnear)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_edges<1>), dim3(f.gx, f.gy), dim3(64 * f.ll.edge_rows), 0, st, f,
+                           n_views, vt, q_min);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_edges<0>), dim3(f.gx, f.gy), dim3(64 * f.ll.edge_rows), 0, st, f,
+                           n_views, vt, q_min);
     return hipGetLastError();
 }
 

@@ -59,7 +59,7 @@ def test_roofline_kernel_names_match_the_profiles():
     assert bench.scan_kernels([200, 400]) == ["k_scanlines<4, 0>", "k_scanlines<8, 0>"]
     assert bench.scan_kernels([1023]) == ["k_scanlines<16, 0>"]
     keys = set(json.load(open(os.path.join(ROOT, "profiles", "traffic.json"))))
-    assert {"k_scanlines<2, 0>", "k_edges"} <= keys
+    assert {"k_scanlines<2, 0>", "k_edges<0>"} <= keys
     for k in keys - {"copy_probe"}:
         base = k.split("<")[0]
         src = open(os.path.join(ROOT, bench.kernel_source(k))).read()
