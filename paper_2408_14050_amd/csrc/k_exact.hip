@@ -474,9 +474,10 @@ struct TileView {
 };
 
 // G (all scanline forms): 1 when the call may use the bilinear sampling
-// variant or a routed frame's tile states (runtime checks), 0 for the plain
-// exact path, where those checks are compiled out (fewer registers: c2 pass
-// 2.93 -> 2.64 ms, c1 25.8 -> 25.3 us).
+// variant, a routed frame's tile states or more than one neighbour per side
+// (runtime checks), 0 for the plain exact path with N = 1, where those checks
+// are compiled out (fewer registers: c2 pass 2.93 -> 2.64 ms, c1 25.8 ->
+// 25.3 us).
 template <int K, int G>
 __device__ __forceinline__ void mark_hit(uint8_t* __restrict__ Mv, int W, int cx, int cy, float c,
                                          float s, int g, TileView tv) {
@@ -684,7 +685,8 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
         const float Wp = Ws[p];
         const float Vp = Vs[p];
         bool hit = false;
-        for (int d = 1; d <= th.ns; ++d) {
+        const int ns = G ? th.ns : 1;  // the plain form serves N = 1 only
+        for (int d = 1; d <= ns; ++d) {
             const int jl = max(p - d, 0), jr = min(p + d, nvalid - 1);
             const float wl = Ws[jl], vl = Vs[jl], wr = Ws[jr], vr = Vs[jr];
             hit |= (p - d >= 0) & (fabsf(__fsub_rn(Wp, wl)) < th.zeta) & (__fsub_rn(vl, Vp) > th.beta);
@@ -1052,16 +1054,17 @@ hipError_t launch_scanlines_batched_g(hipStream_t st, const FrameDesc* table, in
 
 hipError_t launch_scanlines(hipStream_t st, const FrameDesc& f, int n_views, const ViewTable& vt,
                             const Thresholds& th, int cls, int n_blocks) {
-    return (th.bilinear || f.tstate) ? launch_scanlines_g<1>(st, f, n_views, vt, th, cls, n_blocks)
-                                     : launch_scanlines_g<0>(st, f, n_views, vt, th, cls, n_blocks);
+    return (th.bilinear || f.tstate || th.ns != 1) ? launch_scanlines_g<1>(st, f, n_views, vt, th, cls, n_blocks)
+                                                   : launch_scanlines_g<0>(st, f, n_views, vt, th, cls, n_blocks);
 }
 
 // Batched frames are never routed (no tile states).
 hipError_t launch_scanlines_batched(hipStream_t st, const FrameDesc* table, int n_frames,
                                     int n_views, const ViewTable& vt, const Thresholds& th,
                                     int cls, int n_blocks) {
-    return th.bilinear ? launch_scanlines_batched_g<1>(st, table, n_frames, n_views, vt, th, cls, n_blocks)
-                       : launch_scanlines_batched_g<0>(st, table, n_frames, n_views, vt, th, cls, n_blocks);
+    return (th.bilinear || th.ns != 1)
+               ? launch_scanlines_batched_g<1>(st, table, n_frames, n_views, vt, th, cls, n_blocks)
+               : launch_scanlines_batched_g<0>(st, table, n_frames, n_views, vt, th, cls, n_blocks);
 }
 
 }  // namespace occl
