@@ -56,7 +56,7 @@ def test_gpu_median_parity(ref, K):
     ctx = occl.Context(0)
     try:
         rng = np.random.default_rng(100 + K)
-        for H, W in [(37, 53), (1, 1), (960, 1280)]:
+        for H, W in [(37, 53), (1, 1), (3, 4), (960, 1280)]:
             m = (rng.normal(size=(K, H, W)) * 10).astype(np.float32)
             m[rng.uniform(size=m.shape) < 0.2] = np.nan
             if H > 1:
