@@ -497,6 +497,7 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
     const int n = 2 * h + 1;
     float wk[K];
     uint64_t vmask[K];
+    uint32_t pofs[K];  // pixel offset iy * W + ix of each kept sample (H * W < 2^32)
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         // branch-free: the gather address is clamped into the frame and the
@@ -525,6 +526,7 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
             const int cxi = min(max(ix, 0), W - 1), cyi = min(max(iy, 0), H - 1);
             Vr = D[(size_t)cyi * W + cxi];
         }
+        pofs[k] = (uint32_t)iy * (uint32_t)W + (uint32_t)ix;  // used for kept samples only
         const float V = valid ? Vr : 0.0f;
         const float w = valid ? __fsub_rn(gf, __fmul_rn(r, Vr)) : __int_as_float(0x7fc00000);
         L.Vin[e] = V;
@@ -693,7 +695,12 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
             hit |= (p + d < nvalid) & (fabsf(__fsub_rn(Wp, wr)) < th.zeta) &
                    (__fsub_rn(vr, Vp) > th.beta);
         }
-        if (valid & hit) mark_hit<K, G>(Mv, W, cx, cy, c, s, e - h, tv);
+        if (valid & hit) {
+            if constexpr (G)
+                mark_hit<K, G>(Mv, W, cx, cy, c, s, e - h, tv);
+            else
+                Mv[pofs[k]] = 1;  // the pixel the gather read
+        }
     }
     wave_lds_sync();
 }
