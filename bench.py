@@ -494,7 +494,7 @@ def bench_learned(ctx, steps: int, n_eval: int):
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--seed", type=int, default=1002)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
