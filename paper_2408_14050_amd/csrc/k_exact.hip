@@ -874,13 +874,23 @@ __global__ __launch_bounds__(64 * batched_waves_per_block<KMAX>(), min_waves_per
     const int lane = threadIdx.x & 63;
     constexpr int NA = lds_arrays<KMAX>();
     const WaveLds L{lds[wave][0], lds[wave][1], okeys[wave], lds[wave][NA - 2], lds[wave][NA - 1], runs[wave]};
-    // blocked round-robin over the frame-major list (see k_scanlines): all
-    // wavefronts work on neighbouring frames at any time
-    const int nw = gridDim.x * WPB;
-    const int gw = blockIdx.x * WPB + wave;
+    // Workgroups are dealt to the 8 dies (XCDs, each with its own L2) in
+    // turn, so die x = blockIdx % 8 takes the x-th eighth of the frame-major
+    // list: each L2 then holds only its own frames' D.  Within a die, blocked
+    // round-robin (see k_scanlines).  Every item is in exactly one eighth;
+    // with fewer than 8 blocks the whole list is dealt to all of them.
+    constexpr int kDies = 8;
+    const bool split = gridDim.x >= kDies;
+    const int die = split ? (int)(blockIdx.x % kDies) : 0;
+    const int nb = split ? (int)((gridDim.x - die + kDies - 1) / kDies) : (int)gridDim.x;
+    const int bi = split ? (int)(blockIdx.x / kDies) : (int)blockIdx.x;
+    const int c0 = split ? (int)((long long)total * die / kDies) : 0;
+    const int c1 = split ? (int)((long long)total * (die + 1) / kDies) : total;
+    const int nw = nb * WPB;
+    const int gw = bi * WPB + wave;
     int fi = 0;
-    for (int g0 = gw * kGroup; g0 < total; g0 += nw * kGroup) {
-        const int g1 = min(total, g0 + kGroup);
+    for (int g0 = c0 + gw * kGroup; g0 < c1; g0 += nw * kGroup) {
+        const int g1 = min(c1, g0 + kGroup);
         int fi_cur = -1, lo = 0, nseg = 0, seg0 = 0, pbase = 0;
         for (int t = g0; t < g1; ++t) {
             if (fi_cur < 0 || t >= fpre[fi_cur + 1]) {
