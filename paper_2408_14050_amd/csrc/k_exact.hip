@@ -790,30 +790,92 @@ __global__ __launch_bounds__(64 * waves_per_block<KMAX>(), min_waves_per_simd<KM
         }
     }
     __syncthreads();
-    const int total = pre[nseg];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     constexpr int NA = lds_arrays<KMAX>();
     const WaveLds L{lds[wave][0], lds[wave][1], okeys[wave], lds[wave][NA - 2], lds[wave][NA - 1], runs[wave]};
-    // Blocked round-robin: wavefront gw takes groups of kGroup consecutive
-    // items at gw*kGroup, gw*kGroup + nw*kGroup, ...  All wavefronts sweep the
-    // list together (a small live working set of D), and within a group the
-    // segment is found by stepping forward.
-    const int nw = gridDim.x * WPB;
-    const int gw = blockIdx.x * WPB + wave;
-    for (int g0 = gw * kGroup; g0 < total; g0 += nw * kGroup) {
-        const int g1 = min(total, g0 + kGroup);
-        int lo = 0, hi = nseg - 1;  // segment of the group's first item: last with pre <= g0
+    // one item: the class-list index t, its segment found by stepping forward from lo
+    auto item = [&](int t, int& lo) {
+        while (lo + 1 < nseg && pre[lo + 1] <= t) ++lo;
+        const int sv = segvs[lo];
+        const int v = sv >> 16, seg = sv & 0xffff;
+        const uint32_t pix = f.lists[(size_t)seg * f.ll.cap + (size_t)(t - pre[lo])];
+        scan_item<KMAX, G>(f, v, pix, vt, th, L, lane);
+    };
+    auto seg_of = [&](int t) {  // last segment with pre <= t
+        int lo = 0, hi = nseg - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (pre[mid] <= g0) lo = mid; else hi = mid - 1;
+            if (pre[mid] <= t) lo = mid; else hi = mid - 1;
         }
-        for (int t = g0; t < g1; ++t) {
-            while (lo + 1 < nseg && pre[lo + 1] <= t) ++lo;
-            const int sv = segvs[lo];
-            const int v = sv >> 16, seg = sv & 0xffff;
-            const uint32_t pix = f.lists[(size_t)seg * f.ll.cap + (size_t)(t - pre[lo])];
-            scan_item<KMAX, G>(f, v, pix, vt, th, L, lane);
+        return lo;
+    };
+    // Workgroups are dealt to the 8 dies (XCDs, each with its own L2) in
+    // turn.  For a frame whose D exceeds what the dies' L2s hold together,
+    // die x = blockIdx % 8 takes the x-th eighth of every view's items; a
+    // view's items are ordered by row band, so a die works on about one eighth
+    // of the frame's rows of every view (its own part of D in its L2) with the
+    // same mix of scanline lengths as the others (3840x2160 x 15: 2.67 ->
+    // 2.44 ms).  For smaller frames the split costs more than it saves (c1
+    // 34.4 -> 36.8 us), and all wavefronts share one list.
+    constexpr int kDies = 8;
+    constexpr size_t kDieSplitBytes = size_t(16) << 20;
+    const bool split = gridDim.x >= kDies && (size_t)f.H * f.W * sizeof(float) >= kDieSplitBytes;
+    if (!split) {
+        // Blocked round-robin: wavefront gw takes groups of kGroup consecutive
+        // items at gw*kGroup, gw*kGroup + nw*kGroup, ...  All wavefronts sweep
+        // the list together (a small live working set of D), and within a
+        // group the segment is found by stepping forward.
+        const int total = pre[nseg];
+        const int nw = gridDim.x * WPB;
+        const int gw = blockIdx.x * WPB + wave;
+        for (int g0 = gw * kGroup; g0 < total; g0 += nw * kGroup) {
+            const int g1 = min(total, g0 + kGroup);
+            int lo = seg_of(g0);
+            for (int t = g0; t < g1; ++t) item(t, lo);
+        }
+        return;
+    }
+    // dst: die-local prefix over the class's views; gst: class-list index of
+    // the die's first item of each view
+    __shared__ int dst[OCCL_MAX_VIEWS + 1];
+    __shared__ int gst[OCCL_MAX_VIEWS];
+    const int nvc = f.cls_start[cls + 1] - f.cls_start[cls];
+    const int die = (int)(blockIdx.x % kDies);
+    if (threadIdx.x < 64) {  // one wavefront: nvc <= 64
+        const int j = threadIdx.x;
+        int a = 0, cnt = 0;
+        if (j < nvc) {
+            const int vs = pre[j * C], ve = pre[(j + 1) * C];
+            a = vs + (int)((long long)(ve - vs) * die / kDies);
+            cnt = vs + (int)((long long)(ve - vs) * (die + 1) / kDies) - a;
+        }
+        int x = cnt;  // inclusive scan over the views
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(x, d, 64);
+            if (j >= d) x += y;
+        }
+        if (j < nvc) {
+            dst[j] = x - cnt;
+            gst[j] = a;
+        }
+        if (j == nvc - 1) dst[nvc] = x;
+        if (nvc == 0 && j == 0) dst[0] = 0;
+    }
+    __syncthreads();
+    const int total = dst[nvc];
+    // blocked round-robin within the die; view and segment found by stepping forward
+    const int nw = (int)((gridDim.x - die + kDies - 1) / kDies) * WPB;
+    const int gw = (int)(blockIdx.x / kDies) * WPB + wave;
+    for (int g0 = gw * kGroup; g0 < total; g0 += nw * kGroup) {
+        const int g1 = min(total, g0 + kGroup);
+        int j = 0;  // view of the group's first item (last with dst <= g0)
+        while (j + 1 < nvc && dst[j + 1] <= g0) ++j;
+        int lo = seg_of(gst[j] + (g0 - dst[j]));
+        for (int tl = g0; tl < g1; ++tl) {
+            while (j + 1 < nvc && dst[j + 1] <= tl) ++j;
+            item(gst[j] + (tl - dst[j]), lo);
         }
     }
 }
