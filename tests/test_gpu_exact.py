@@ -409,3 +409,16 @@ def test_maximum_frame_extent(gctx, torch, ref, shape):
     np.testing.assert_array_equal(nc, nc_ref)
     assert nc.sum() > 0
     assert_parity(M, M_ref, None, f"{H}x{W}")
+
+
+@pytest.mark.parametrize("seed", [4242, 4243])
+def test_large_frame_split_over_dies(gctx, torch, ref, seed):
+    """A 2048 x 2048 frame (D of 16 MiB, where the scanline pass splits each
+    view's items over the dies), c1 statistics, 8 views: the whole mask equals
+    the oracle's."""
+    sc = scenes.make_c1_like(seed, W=2048, H=2048)
+    assert sc.D.nbytes >= 16 << 20
+    M_ref, _, nc_ref = ref.detect_scene(sc)
+    M, nc = run_gpu(gctx, torch, sc.D, sc.angles, sc.ratios, sc.scan_len, counts=True, **sc.params)
+    np.testing.assert_array_equal(nc, nc_ref)
+    assert_parity(M, M_ref, None, f"2048x2048 seed {seed}")
