@@ -86,9 +86,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // fp32 <-> totally ordered uint32 (ascending float order = ascending uint order)
 __device__ __forceinline__ uint32_t f2ord(float w) {
-    uint32_t u = __float_as_uint(w);
-    if (u == 0x80000000u) u = 0u;  // -0 sorts as +0
-    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    const uint32_t u = __float_as_uint(__fadd_rn(w, 0.0f));  // -0 + 0 = +0: -0 sorts as +0
+    return u ^ ((uint32_t)((int32_t)u >> 31) | 0x80000000u);  // negative: ~u; else u | sign
 }
 __device__ __forceinline__ float ord2f(uint32_t o) {
     const uint32_t u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
@@ -508,7 +507,8 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
         const float py = __fadd_rn((float)cy, __fmul_rn(s, gf));
         const int ix = (int)rintf(px);
         const int iy = (int)rintf(py);
-        const bool valid = (e < n) & (ix >= 0) & (ix < W) & (iy >= 0) & (iy < H);
+        const bool valid = (e < n) & ((uint32_t)ix < (uint32_t)W) & ((uint32_t)iy < (uint32_t)H);
+        const uint32_t po = (uint32_t)iy * (uint32_t)W + (uint32_t)ix;  // H * W < 2^32
         float Vr;
         if (G && th.bilinear) {  // variant: bilinear V at (px, py), taps clamped into the frame
             const float fx0 = floorf(px), fy0 = floorf(py);
@@ -523,10 +523,9 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
             const float bot = __fadd_rn(__fmul_rn(gx, cc), __fmul_rn(fx, d));
             Vr = __fadd_rn(__fmul_rn(gy, top), __fmul_rn(fy, bot));
         } else {
-            const int cxi = min(max(ix, 0), W - 1), cyi = min(max(iy, 0), H - 1);
-            Vr = D[(size_t)cyi * W + cxi];
+            Vr = D[valid ? po : 0u];  // a dropped sample reads pixel 0 and is discarded
         }
-        pofs[k] = (uint32_t)iy * (uint32_t)W + (uint32_t)ix;  // used for kept samples only
+        pofs[k] = po;  // used for kept samples only
         const float V = valid ? Vr : 0.0f;
         const float w = valid ? __fsub_rn(gf, __fmul_rn(r, Vr)) : __int_as_float(0x7fc00000);
         L.Vin[e] = V;
