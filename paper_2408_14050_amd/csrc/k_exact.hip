@@ -496,6 +496,7 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
     const int n = 2 * h + 1;
     float wk[K];
     uint64_t vmask[K];
+    bool kept[K];  // this lane's sample of slot k is in the frame (the bit of vmask[k])
     uint32_t pofs[K];  // pixel offset iy * W + ix of each kept sample (H * W < 2^32)
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -533,6 +534,7 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
         L.Oin[e] = f2ord(w);
         wk[k] = w;
         vmask[k] = __ballot(valid);
+        kept[k] = valid;
     }
     wave_lds_sync();
     // descents W_e < W_{e-1} (both kept; NaN compares false): they split the
@@ -587,10 +589,10 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int e0 = k * 64 + lane;
-            const bool valid = (vmask[k] >> lane) & 1ull;
+            const bool valid = kept[k];
             e_[k] = valid ? e0 : e_lo;  // dropped lanes ride on a kept sample
-            const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
-            own_[k] = valid ? before + __popcll(dm[k] & le) : 0;
+            // run index: descents at offsets <= e (below this lane, and its own)
+            own_[k] = valid ? before + (int)lanes_below(dm[k]) + (int)((dm[k] >> lane) & 1ull) : 0;
             before += __popcll(dm[k]);
             oe_[k] = f2ord(wk[k]);
             pos_[k] = e_[k] - L.rs[own_[k]];
@@ -635,7 +637,7 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             pk[k] = pos_[k];
-            if ((vmask[k] >> lane) & 1ull) {
+            if (kept[k]) {
                 L.Ws[pos_[k]] = wk[k];
                 L.Vs[pos_[k]] = vv[k];
             }
@@ -649,7 +651,7 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const uint32_t e = (uint32_t)(k * 64 + lane);
-            key[k] = ((vmask[k] >> lane) & 1ull) ? (((uint64_t)f2ord(wk[k]) << 32) | e) : ~0ull;
+            key[k] = kept[k] ? (((uint64_t)f2ord(wk[k]) << 32) | e) : ~0ull;
         }
         bitonic_sort<K>(key, lane);
         // the sorted array holds the origin of position p in key[k]; scatter the
@@ -681,7 +683,7 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int e = k * 64 + lane;
-        const bool valid = (vmask[k] >> lane) & 1ull;
+        const bool valid = kept[k];
         const int p = valid ? pk[k] : 0;
         const float Wp = Ws[p];
         const float Vp = Vs[p];
