@@ -494,7 +494,7 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
                                          const WaveLds& L, int lane) {
     constexpr int N = 64 * K;
     const int n = 2 * h + 1;
-    float wk[K];
+    float wk[K], vk[K];  // this lane's W and V of slot k
     uint64_t vmask[K];
     bool kept[K];  // this lane's sample of slot k is in the frame (the bit of vmask[k])
     uint32_t pofs[K];  // pixel offset iy * W + ix of each kept sample (H * W < 2^32)
@@ -533,6 +533,7 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
         L.Win[e] = w;  // NaN: dropped
         L.Oin[e] = f2ord(w);
         wk[k] = w;
+        vk[k] = V;
         vmask[k] = __ballot(valid);
         kept[k] = valid;
     }
@@ -685,8 +686,9 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
         const int e = k * 64 + lane;
         const bool valid = kept[k];
         const int p = valid ? pk[k] : 0;
-        const float Wp = Ws[p];
-        const float Vp = Vs[p];
+        // every route wrote this sample's own W and V at its sorted position p
+        const float Wp = wk[k];
+        const float Vp = vk[k];
         bool hit = false;
         const int ns = G ? th.ns : 1;  // the plain form serves N = 1 only
         for (int d = 1; d <= ns; ++d) {
