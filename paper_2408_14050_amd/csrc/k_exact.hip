@@ -631,16 +631,14 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
                     pos_[k0 + j] += base[j] - s0[j] + ((L.Oin[base[j]] < T[j]) ? 1 : 0);
             }
         }
-        // every read of Vin before the first write: Vs may share Vin's storage
-        float vv[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) vv[k] = L.Vin[e_[k]];
+        // a kept sample writes its own W and V (registers) at its sorted
+        // position; nothing reads Vin any more (Vs may share its storage)
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             pk[k] = pos_[k];
             if (kept[k]) {
                 L.Ws[pos_[k]] = wk[k];
-                L.Vs[pos_[k]] = vv[k];
+                L.Vs[pos_[k]] = vk[k];
             }
         }
         Ws = L.Ws;
