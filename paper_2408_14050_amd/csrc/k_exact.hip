@@ -446,12 +446,10 @@ __device__ __forceinline__ void bitonic_sort(uint64_t (&key)[K], int lane) {
 }
 
 struct WaveLds {
-    float* Vin;  // V by offset index e
-    float* Win;  // W by e (NaN where the sample is dropped)
+    float2* WVin;   // (W, V) by offset index e (W NaN where the sample is dropped)
     uint32_t* Oin;  // f2ord(W) by e (the search keys of the co-rank merge)
-    float* Ws;   // W in sorted order (sort path)
-    float* Vs;   // V in sorted order (sort path)
-    int* rs;     // run starts (co-rank path), kMaxRunsCap + 1 entries
+    float2* WVs;    // (W, V) in sorted order (merge and sort paths)
+    int* rs;        // run starts (co-rank path), kMaxRunsCap + 1 entries
 };
 
 constexpr int kMaxRunsCap = 16;
@@ -529,8 +527,7 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
         pofs[k] = po;  // used for kept samples only
         const float V = valid ? Vr : 0.0f;
         const float w = valid ? __fsub_rn(gf, __fmul_rn(r, Vr)) : __int_as_float(0x7fc00000);
-        L.Vin[e] = V;
-        L.Win[e] = w;  // NaN: dropped
+        L.WVin[e] = make_float2(w, V);  // W NaN: dropped
         L.Oin[e] = f2ord(w);
         wk[k] = w;
         vk[k] = V;
@@ -545,7 +542,7 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int e = k * 64 + lane;
-        const float wp = (e > 0) ? L.Win[e - 1] : __int_as_float(0x7fc00000);
+        const float wp = (e > 0) ? L.WVin[e - 1].x : __int_as_float(0x7fc00000);
         dm[k] = __ballot(wk[k] < wp);
         ndesc += __popcll(dm[k]);
         nvalid += __popcll(vmask[k]);
@@ -555,16 +552,14 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
     const int e_hi = e_lo + nvalid - 1;  // the kept offsets are one contiguous run
     const int R = ndesc + 1;
 
-    // sorted position of every kept sample (pk) and the sorted arrays Ws, Vs
+    // sorted position of every kept sample (pk) and the sorted pairs WVs
     int pk[K];
-    const float* Ws;
-    const float* Vs;
+    const float2* WVs;
     if (R == 1) {
         // already in (W, g) order: sorted position p is offset e_lo + p
 #pragma unroll
         for (int k = 0; k < K; ++k) pk[k] = k * 64 + lane - e_lo;
-        Ws = L.Win + e_lo;
-        Vs = L.Vin + e_lo;
+        WVs = L.WVin + e_lo;
     } else if (R <= max_runs<K>()) {
         // ---- co-rank merge: every run is sorted by (W, e); the sorted position
         // of sample e is its index in its own run plus, for every other run,
@@ -631,18 +626,16 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
                     pos_[k0 + j] += base[j] - s0[j] + ((L.Oin[base[j]] < T[j]) ? 1 : 0);
             }
         }
-        // a kept sample writes its own W and V (registers) at its sorted
-        // position; nothing reads Vin any more (Vs may share its storage)
+        // a kept sample writes its own (W, V) (registers) at its sorted
+        // position; nothing reads WVin any more (WVs may share its storage)
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             pk[k] = pos_[k];
             if (kept[k]) {
-                L.Ws[pos_[k]] = wk[k];
-                L.Vs[pos_[k]] = vk[k];
+                L.WVs[pos_[k]] = make_float2(wk[k], vk[k]);
             }
         }
-        Ws = L.Ws;
-        Vs = L.Vs;
+        WVs = L.WVs;
         wave_lds_sync();
     } else {
         // ---- many runs: bitonic sort of (W, e) keys ----
@@ -655,27 +648,25 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
         bitonic_sort<K>(key, lane);
         // the sorted array holds the origin of position p in key[k]; scatter the
         // inverse (origin -> position) into the key array, unused on this
-        // path, so the test below runs per kept sample.  Every read of Vin
-        // comes before the first write (Vs may share Vin's storage).
+        // path, so the test below runs per kept sample.  Every read of WVin
+        // comes before the first write (WVs may share WVin's storage).
         float vv[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) vv[k] = L.Vin[(k * 64 + lane < nvalid) ? (uint32_t)key[k] : 0u];
+        for (int k = 0; k < K; ++k) vv[k] = L.WVin[(k * 64 + lane < nvalid) ? (uint32_t)key[k] : 0u].y;
         int* inv = reinterpret_cast<int*>(L.Oin);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int p = k * 64 + lane;
             if (p < nvalid) {
                 const uint32_t o = (uint32_t)key[k];
-                L.Ws[p] = ord2f((uint32_t)(key[k] >> 32));
-                L.Vs[p] = vv[k];
+                L.WVs[p] = make_float2(ord2f((uint32_t)(key[k] >> 32)), vv[k]);
                 inv[o] = p;
             }
         }
         wave_lds_sync();
 #pragma unroll
         for (int k = 0; k < K; ++k) pk[k] = inv[min(k * 64 + lane, N - 1)];
-        Ws = L.Ws;
-        Vs = L.Vs;
+        WVs = L.WVs;
         wave_lds_sync();
     }
     // Eq. (5) at every kept sample's sorted position, Eq. (6) at its pixel
@@ -691,7 +682,8 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
         const int ns = G ? th.ns : 1;  // the plain form serves N = 1 only
         for (int d = 1; d <= ns; ++d) {
             const int jl = max(p - d, 0), jr = min(p + d, nvalid - 1);
-            const float wl = Ws[jl], vl = Vs[jl], wr = Ws[jr], vr = Vs[jr];
+            const float2 nl = WVs[jl], nr = WVs[jr];
+            const float wl = nl.x, vl = nl.y, wr = nr.x, vr = nr.y;
             hit |= (p - d >= 0) & (fabsf(__fsub_rn(Wp, wl)) < th.zeta) & (__fsub_rn(vl, Vp) > th.beta);
             hit |= (p + d < nvalid) & (fabsf(__fsub_rn(Wp, wr)) < th.zeta) &
                    (__fsub_rn(vr, Vp) > th.beta);
@@ -718,13 +710,13 @@ constexpr int waves_per_block() { return KMAX >= 16 ? 2 : 4; }
 template <int KMAX>
 constexpr int min_waves_per_simd() { return KMAX <= 2 ? 8 : 1; }
 
-// Float arrays per wavefront in LDS: Vin, Win, and the sorted Vs, Ws.  The
-// long-scanline forms are limited by LDS, so their sorted arrays share the
-// input arrays' storage (every path reads what it needs of the inputs before
-// writing the sorted values); c2 (K = 8) then fits 4 blocks per CU instead
-// of 3.
+// (W, V) pair arrays per wavefront in LDS: the inputs WVin and the sorted
+// WVs.  The long-scanline forms are limited by LDS, so their sorted array
+// shares the input array's storage (every path reads what it needs of the
+// inputs before writing the sorted values); c2 (K = 8) then fits 4 blocks per
+// CU instead of 3.
 template <int KMAX>
-constexpr int lds_arrays() { return KMAX >= 4 ? 2 : 4; }
+constexpr int lds_arrays() { return KMAX >= 4 ? 1 : 2; }
 
 constexpr int kGroup = 4;  // consecutive work items per wavefront visit
 
@@ -774,7 +766,7 @@ __global__ __launch_bounds__(64 * waves_per_block<KMAX>(), min_waves_per_simd<KM
     FrameDesc f, int n_views, ViewTable vt, Thresholds th, int cls) {
     constexpr int WPB = waves_per_block<KMAX>();
     constexpr int NT = 64 * WPB;
-    __shared__ float lds[WPB][lds_arrays<KMAX>()][64 * KMAX];
+    __shared__ float2 lds[WPB][lds_arrays<KMAX>()][64 * KMAX];
     __shared__ uint32_t okeys[WPB][64 * KMAX];
     __shared__ int runs[WPB][kMaxRunsCap + 1];
     __shared__ int pre[kMaxSegments + 1];
@@ -794,7 +786,7 @@ __global__ __launch_bounds__(64 * waves_per_block<KMAX>(), min_waves_per_simd<KM
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     constexpr int NA = lds_arrays<KMAX>();
-    const WaveLds L{lds[wave][0], lds[wave][1], okeys[wave], lds[wave][NA - 2], lds[wave][NA - 1], runs[wave]};
+    const WaveLds L{lds[wave][0], okeys[wave], lds[wave][NA - 1], runs[wave]};
     // one item: the class-list index t, its segment found by stepping forward from lo
     auto item = [&](int t, int& lo) {
         while (lo + 1 < nseg && pre[lo + 1] <= t) ++lo;
@@ -890,7 +882,7 @@ __global__ __launch_bounds__(64 * batched_waves_per_block<KMAX>(), min_waves_per
     int cls) {
     constexpr int WPB = batched_waves_per_block<KMAX>();
     constexpr int NT = 64 * WPB;
-    __shared__ float lds[WPB][lds_arrays<KMAX>()][64 * KMAX];
+    __shared__ float2 lds[WPB][lds_arrays<KMAX>()][64 * KMAX];
     __shared__ uint32_t okeys[WPB][64 * KMAX];
     __shared__ int runs[WPB][kMaxRunsCap + 1];
     __shared__ int fpre[kMaxBatch + 1];
@@ -936,7 +928,7 @@ __global__ __launch_bounds__(64 * batched_waves_per_block<KMAX>(), min_waves_per
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     constexpr int NA = lds_arrays<KMAX>();
-    const WaveLds L{lds[wave][0], lds[wave][1], okeys[wave], lds[wave][NA - 2], lds[wave][NA - 1], runs[wave]};
+    const WaveLds L{lds[wave][0], okeys[wave], lds[wave][NA - 1], runs[wave]};
     // Workgroups are dealt to the 8 dies (XCDs, each with its own L2) in
     // turn, so die x = blockIdx % 8 takes the x-th eighth of the frame-major
     // list: each L2 then holds only its own frames' D.  Within a die, blocked
