@@ -16,17 +16,22 @@
 //   scanline pass    one wavefront per candidate scanline (Eqs. 4-6), the
 //                    (view, candidate) pairs handed out flat in small groups,
 //                    round-robin, so long and short lists balance and all
-//                    wavefronts sweep the list (and D) together.
+//                    wavefronts sweep the list (and D) together; for large
+//                    frames and for batches each die (XCD) takes its own
+//                    eighth of the list so that its L2 holds its part of D.
 //                    A scanline of n <= 64*K samples holds K samples per lane.
 //                    Ordering by (W, g): W split into maximal non-decreasing
 //                    runs; one run is already sorted; up to a few runs are
 //                    merged by co-ranks (binary search of every sample in the
 //                    other runs); otherwise a bitonic sort whose partners are
-//                    reached with DPP and permlane swaps.  The sorted W and V
-//                    go through LDS for the neighbour test of Eq. (5); hits
+//                    reached with DPP and permlane swaps.  The sorted (W, V)
+//                    pairs go through LDS for the neighbour test of Eq. (5); hits
 //                    are byte stores of 1 into the cleared mask, so
 //                    concurrent scanlines need no atomics and the result
 //                    does not depend on order.
+// Each pass has a plain form (the exact path with N = 1, no bilinear
+// sampling, no routed tiles) and a general form with those runtime checks;
+// the host picks the plain one whenever a call allows it.
 //
 // Every fp32 operation that feeds a decision is an explicitly rounded
 // intrinsic (__fmul_rn, __fadd_rn, __fsub_rn) and the library is built with
