@@ -138,10 +138,12 @@ float bilinear_sample(const float* D, int H, int W, float px, float py) {
     return (1.0f - fy) * top + fy * bot;
 }
 
+// The window is g = -h .. hi (hi = h except in the thinning variant).
 void build_scanline(const float* D, int H, int W, int cx, int cy, float c, float s,
-                    float r, int h, std::vector<Sample>& out, bool bilinear = false) {
+                    float r, int h, std::vector<Sample>& out, bool bilinear = false, int hi = -1) {
     out.clear();
-    for (int g = -h; g <= h; ++g) {
+    if (hi < 0) hi = h;
+    for (int g = -h; g <= hi; ++g) {
         float gf = (float)g;
         float tx = c * gf;
         float ty = s * gf;
@@ -181,6 +183,19 @@ void sort_and_test(std::vector<Sample>& smp, float zeta, float beta, int ns,
         }
         hit[k] = (O > 0) ? 1 : 0;
     }
+}
+
+// Pixel of scanline offset g of candidate (cx, cy) (Eq. (4), R5); false
+// when it falls outside the frame.
+bool scanline_pixel(int cx, int cy, float c, float s, int g, int H, int W, int* ix, int* iy) {
+    float gf = (float)g;
+    float tx = c * gf;
+    float ty = s * gf;
+    float px = (float)cx + tx;
+    float py = (float)cy + ty;
+    *ix = (int)std::rint(px);
+    *iy = (int)std::rint(py);
+    return *ix >= 0 && *ix < W && *iy >= 0 && *iy < H;
 }
 
 inline int neighbours_per_side(int N) {
@@ -343,14 +358,28 @@ int occl_ref_detect(const float* D, int H, int W, int n_views, const double* ang
 
 /* occl_ref_detect with variant flags: bit 0 = bilinear V sampling (see
  * bilinear_sample; the tight map then covers the nearest-pixel decisions
- * only). */
+ * only); bit 1 = candidate thinning (below; needs tight == NULL).
+ *
+ * Candidate thinning (variant, not the paper's method: its summary, Sec. 6, names
+ * a thinner candidate list as future work).  Collinear candidates share most of their
+ * scanline, so their scanlines are merged:
+ *   - a candidate whose scanline pixel at g = -1 is itself a candidate of the
+ *     same view (Eq. (2)) is a follower and is not scanned;
+ *   - every other candidate scans g = -h .. h + m instead of -h .. h, where m
+ *     is the number of consecutive candidates of the view at g = 1, 2, ...
+ *     (m <= h; a pixel outside the frame ends the run).
+ * Everything else (sampling, warp, sort, Eq. (5), Eq. (6)) is unchanged.  On
+ * axis directions the merged window is exactly the union of the followers'
+ * windows; in other directions the followers' rounded pixels can differ
+ * from the head's, so the result is an approximation of the method's mask. */
 int occl_ref_detect_ex(const float* D, int H, int W, int n_views, const double* angles,
                        const float* ratios, const int* scan_len, float gamma, float beta,
                        float zeta, int neighbours, unsigned char* M, unsigned char* tight,
                        long long* n_cand, int flags) {
     const bool bilinear = (flags & 1) != 0;
+    const bool thin = (flags & 2) != 0;
     if (!D || !angles || !ratios || !scan_len || !M || H < 1 || W < 1 || n_views < 1 ||
-        neighbours < 1)
+        neighbours < 1 || (thin && tight))
         return -1;
     for (int v = 0; v < n_views; ++v)
         if (scan_len[v] < 1 || !(ratios[v] > 0.0f) || !std::isfinite(angles[v])) return -1;
@@ -371,6 +400,7 @@ int occl_ref_detect_ex(const float* D, int H, int W, int n_views, const double* 
 
     std::vector<Sample> smp;
     std::vector<unsigned char> hit;
+    std::vector<unsigned char> candv(thin ? HW : 0);
     for (int v = 0; v < n_views; ++v) {
         float c, s;
         ref_direction(angles[v], &c, &s);
@@ -379,6 +409,9 @@ int occl_ref_detect_ex(const float* D, int H, int W, int n_views, const double* 
         unsigned char* Mv = M + HW * v;
         unsigned char* Tv = tight ? tight + HW * v : nullptr;
         long long nc = 0;
+        if (thin)  // Eq. (2) over the whole frame, for the follower / run tests
+            for (size_t i = 0; i < HW; ++i)
+                candv[i] = is_candidate(E[i], edge_dot(ex[i], ey[i], c, s), gamma) ? 1 : 0;
         for (int y = 0; y < H; ++y)
             for (int x = 0; x < W; ++x) {
                 size_t i = (size_t)y * W + x;
@@ -390,7 +423,20 @@ int occl_ref_detect_ex(const float* D, int H, int W, int n_views, const double* 
                                  (std::fabs(dot) < kTightEps && E[i] > gamma - kTightEps);
                 }
                 if (!cand && !cand_tight) continue;
-                build_scanline(D, H, W, x, y, c, s, r, h, smp, bilinear);  // Eq. (4) + V
+                int hi = h;
+                if (thin) {
+                    int px, py;
+                    if (scanline_pixel(x, y, c, s, -1, H, W, &px, &py) && candv[(size_t)py * W + px]) {
+                        ++nc;  // a follower: counted as a candidate, not scanned
+                        continue;
+                    }
+                    int m = 0;
+                    while (m < h && scanline_pixel(x, y, c, s, m + 1, H, W, &px, &py) &&
+                           candv[(size_t)py * W + px])
+                        ++m;
+                    hi = h + m;
+                }
+                build_scanline(D, H, W, x, y, c, s, r, h, smp, bilinear, hi);  // Eq. (4) + V
                 if (cand_tight) {
                     for (const Sample& sm : smp) Tv[(size_t)sm.iy * W + sm.ix] = 1;
                 }

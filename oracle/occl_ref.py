@@ -132,9 +132,10 @@ def scan_len(D, ratios, mode: int = 0):
 
 
 def detect(D, angles, ratios, scan_len, edge_thr=1.0, disp_thr=0.5, dist_thr=1.0,
-           neighbours=1, want_tight=False, bilinear=False):
+           neighbours=1, want_tight=False, bilinear=False, thin=False):
     """Returns (M [V,H,W] uint8, tight or None, n_cand [V] int64).
-    bilinear: the bilinear-V variant (occl_ref_detect_ex flag 1)."""
+    bilinear: the bilinear-V variant (occl_ref_detect_ex flag 1).
+    thin: the candidate-thinning variant (flag 2; no tight map)."""
     D = _f32(D)
     H, W = D.shape
     a = np.ascontiguousarray(np.atleast_1d(angles), dtype=np.float64)
@@ -147,7 +148,7 @@ def detect(D, angles, ratios, scan_len, edge_thr=1.0, disp_thr=0.5, dist_thr=1.0
     rc = lib().occl_ref_detect_ex(_p(D, C.c_float), H, W, V, _p(a, C.c_double), _p(r, C.c_float),
                                   _p(Ls, C.c_int), float(edge_thr), float(disp_thr), float(dist_thr),
                                   int(neighbours), _p(M, C.c_ubyte), _p(T, C.c_ubyte),
-                                  _p(nc, C.c_longlong), 1 if bilinear else 0)
+                                  _p(nc, C.c_longlong), (1 if bilinear else 0) | (2 if thin else 0))
     if rc != 0:
         raise ValueError("invalid argument to occl_ref_detect")
     return M, T, nc

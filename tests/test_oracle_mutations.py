@@ -48,13 +48,23 @@ MUTANTS = {
     "zbuffer_target_sign": ("const long long tx = (long long)std::nearbyint((float)x - t * c);",
                             "const long long tx = (long long)std::nearbyint((float)x + t * c);"),
     "zbuffer_non_strict": ("(best[i] - D[i] > beta) ? 1 : 0;", "(best[i] - D[i] >= beta) ? 1 : 0;"),
+    # candidate thinning (variant)
+    "thin_followers_scanned": ("if (scanline_pixel(x, y, c, s, -1, H, W, &px, &py) && candv[(size_t)py * W + px]) {",
+                               "if (false && scanline_pixel(x, y, c, s, -1, H, W, &px, &py)) {"),
+    "thin_run_uncapped": ("while (m < h && scanline_pixel(", "while (m < 2 * h && scanline_pixel("),
+    "thin_no_extension": ("hi = h + m;", "hi = h;"),
+    "thin_run_backwards": ("scanline_pixel(x, y, c, s, m + 1, H, W, &px, &py)",
+                           "scanline_pixel(x, y, c, s, -(m + 1), H, W, &px, &py)"),
+    "thin_candidate_map_transposed": ("candv[(size_t)py * W + px]) {",
+                                      "candv[((size_t)px * W + py) % HW]) {"),
     # median fusion
     "median_even_takes_lower": ("(v[m / 2 - 1] + v[m / 2]) * 0.5f", "v[m / 2 - 1]"),
     "median_keeps_nan": ("if (!std::isnan(x)) v.push_back(x);", "v.push_back(x);"),
 }
 
 # every CPU pin file that exercises the oracle
-PIN_FILES = ("test_oracle_pins.py", "test_bilinear.py", "test_quality_oracle.py", "test_fusion.py")
+PIN_FILES = ("test_oracle_pins.py", "test_bilinear.py", "test_quality_oracle.py", "test_fusion.py",
+             "test_thin_oracle.py")
 
 
 @pytest.mark.slow
