@@ -358,7 +358,9 @@ def bench_quality(ctx, n_frames: int = 4):
     out = {"workload": f"c1 1280x960 x8 views seeds 1000..{1000 + n_frames - 1}",
            "reference": "forward-warping z-buffer (nearest target pixel, beta 0.5)"}
     for name, mode, extra in (("scan_len_config", 0, 0), ("scan_len_eq3", -1, 0),
-                              ("scan_len_eq3_bilinear", -1, occl.FLAG_BILINEAR)):
+                              ("scan_len_eq3_bilinear", -1, occl.FLAG_BILINEAR),
+                              ("scan_len_config_thin", 0, occl.FLAG_THIN),
+                              ("scan_len_eq3_thin", -1, occl.FLAG_THIN)):
         acc = [0, 0, 0, 0]
         per_frame = []
         for k in range(n_frames):
@@ -388,6 +390,37 @@ def bench_quality(ctx, n_frames: int = 4):
         ctx.occl_zbuffer(D, sc.angles, sc.ratios, 0.5, M=Z)
     torch.cuda.synchronize()
     out["zbuffer_ms"] = round((time.perf_counter() - t0) / 20 * 1e3, 4)
+    return out
+
+
+def bench_thin(ctx, seed: int, steps: int = 500, prewarm: int = 300):
+    """Candidate thinning (OCCL_FLAG_THIN, a variant) on one c1 frame at a
+    time: ms per frame beside the exact path on the same context and stream,
+    the scanline pass alone, and how far the mask moves from the exact one."""
+    import torch
+    from paper_2408_14050_amd import occl, scenes
+    sc = scenes.make_scene("c1", seed)
+    D = torch.from_numpy(sc.D).cuda()
+    out = {"workload": f"c1 1280x960 x8 views seed {seed}, configured L, one frame at a time"}
+    masks = {}
+    for name, fl in (("exact", 0), ("thin", occl.FLAG_THIN)):
+        prm = occl.params(**sc.params, scan_len_per_view=sc.scan_len, flags=fl)
+        f = ctx.occl_detect_prepared(sc.angles, sc.ratios, prm)
+        M = torch.empty((len(sc.angles),) + sc.D.shape, dtype=torch.uint8, device="cuda")
+        for _ in range(prewarm):
+            f(D, M)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            f(D, M)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        out[name] = {"ms": round(ms, 4), "scanline_pass_ms": round(ctx.occl_time_scanlines(200), 4)}
+        masks[name] = M.clone()
+    c = ctx.occl_confusion(masks["thin"], masks["exact"])
+    out["vs_exact"] = {"differing_bytes": int(c["fp"] + c["fn"]),
+                       "iou": round(c["tp"] / max(1, c["tp"] + c["fp"] + c["fn"]), 5)}
+    out["speedup_vs_exact"] = round(out["exact"]["ms"] / out["thin"]["ms"], 3)
     return out
 
 
@@ -541,8 +574,8 @@ def main() -> int:
         return 0
     if args.quality_only:
         ctx = occl.Context(0)
-        print(json.dumps({"quality_vs_zbuffer": bench_quality(ctx), "median_fusion": bench_fusion(ctx)}),
-              flush=True)
+        print(json.dumps({"quality_vs_zbuffer": bench_quality(ctx), "median_fusion": bench_fusion(ctx),
+                          "thinning": bench_thin(ctx, args.seed)}), flush=True)
         ctx.occl_release()
         return 0
     sc = scenes.make_scene("c1", args.seed)
@@ -704,6 +737,7 @@ def main() -> int:
     if not args.no_quality:
         out["quality_vs_zbuffer"] = bench_quality(ctx)
         out["median_fusion"] = bench_fusion(ctx)
+        out["thinning"] = bench_thin(ctx, args.seed)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)

@@ -73,6 +73,16 @@ typedef enum {
                                         scanline position (taps clamped into the frame; top row,
                                         bottom row, then vertical blend, fp32 without FMA); kept
                                         samples and marked pixels stay the nearest pixels */
+#define OCCL_FLAG_THIN 16u           /* variant, an approximation of the method (the thinner
+                                        candidate list the paper's summary, Sec. 6, leaves for
+                                        future work): a candidate whose scanline pixel at g = -1 is
+                                        a candidate of the same view (Eq. 2) is not scanned; every
+                                        other candidate scans g = -h .. h + m, m = the number of
+                                        consecutive candidates at g = 1, 2, ... (at most h; a pixel
+                                        outside the frame ends the run).  occl_detect only, without
+                                        OCCL_FLAG_USE_CNN (else OCCL_ERR_UNSUPPORTED); L at most
+                                        OCCL_THIN_MAX_SCAN_LEN.  Composes with N and bilinear V. */
+#define OCCL_THIN_MAX_SCAN_LEN 683   /* 3 * floor(L / 2) + 1 <= 1024 samples per scanline */
 
 /* Detector parameters (Sec. 3: gamma of Eq. 2, zeta and beta of Eq. 5,
  * N of Eq. 5, L of Eqs. 3-4). */

@@ -494,13 +494,62 @@ __device__ __forceinline__ void mark_hit(uint8_t* __restrict__ Mv, int W, int cx
     Mv[(size_t)iy * W + ix] = 1;
 }
 
+// Eq. (2) at the pixel of scanline offset g (Eq. (4) rounding), with the
+// edge pass's arithmetic: false outside the frame.
+__device__ __forceinline__ bool candidate_at(const float* __restrict__ D, int H, int W, int cx, int cy,
+                                             float c, float s, int g, float q_min) {
+    const float gf = (float)g;
+    const int ix = (int)rintf(__fadd_rn((float)cx, __fmul_rn(c, gf)));
+    const int iy = (int)rintf(__fadd_rn((float)cy, __fmul_rn(s, gf)));
+    if ((uint32_t)ix >= (uint32_t)W || (uint32_t)iy >= (uint32_t)H) return false;
+    const size_t o = (size_t)iy * W + ix;
+    const float d = D[o];
+    const float ex = (ix + 1 < W) ? __fsub_rn(D[o + 1], d) : 0.0f;
+    const float ey = (iy + 1 < H) ? __fsub_rn(D[o + W], d) : 0.0f;
+    const float q = __fadd_rn(__fmul_rn(ex, ex), __fmul_rn(ey, ey));
+    const float dot = __fadd_rn(__fmul_rn(ex, c), __fmul_rn(ey, s));
+    return (q >= q_min) && (dot > 0.0f);
+}
+
+// Candidate thinning (variant): the number of samples of the candidate's
+// merged window, or 0 for a follower.  A candidate whose pixel at g = -1 is
+// itself a candidate is a follower (its scanline is covered by the head of
+// its run); any other candidate scans g = -h .. h + m over the run of m <= h
+// candidates at g = 1, 2, ...  Lane t of a 64-offset chunk tests offset t
+// (t = 0 stands for g = -1); the run is the trailing ones of the ballots.
+__device__ __forceinline__ int thin_window(const float* __restrict__ D, int H, int W, int cx, int cy, float c,
+                                           float s, int h, float q_min, int lane) {
+    int m = 0;
+    for (int t0 = 0; t0 <= h; t0 += 64) {
+        const int t = t0 + lane;
+        const bool is_c = (t <= h) && candidate_at(D, H, W, cx, cy, c, s, t == 0 ? -1 : t, q_min);
+        uint64_t b = __ballot(is_c);
+        if (t0 == 0) {
+            if (b & 1ull) return 0;  // follower
+            b |= 1ull;               // the candidate itself opens the run
+        }
+        const uint64_t gap = ~b;
+        if (gap == 0) {
+            m += (t0 == 0) ? 63 : 64;
+            continue;
+        }
+        m += (__ffsll((unsigned long long)gap) - 1) - (t0 == 0 ? 1 : 0);
+        break;
+    }
+    return 2 * h + 1 + m;  // offsets t > h are never candidates, so m <= h
+}
+
 template <int K, int G>
 __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int W,
                                          uint8_t* __restrict__ Mv, TileView tv, int cx, int cy, float c,
                                          float s, float r, int h, const Thresholds& th,
                                          const WaveLds& L, int lane) {
     constexpr int N = 64 * K;
-    const int n = 2 * h + 1;
+    int n = 2 * h + 1;  // samples of the window g = -h .. n - 1 - h
+    if (G && th.thin) {
+        n = thin_window(D, H, W, cx, cy, c, s, h, th.q_min, lane);
+        if (n == 0) return;  // uniform: a follower is not scanned
+    }
     float wk[K], vk[K];  // this lane's W and V of slot k
     uint64_t vmask[K];
     bool kept[K];  // this lane's sample of slot k is in the frame (the bit of vmask[k])
@@ -749,7 +798,7 @@ __device__ __forceinline__ void scan_item(const FrameDesc& f, int v, uint32_t pi
     TileView tv{nullptr, f.tiles_x};
     if (G && f.tstate) tv.t = f.tstate + (size_t)v * ((H + kTile - 1) / kTile) * f.tiles_x;
     if constexpr (KMAX == 2) {
-        if (lanes_per_scanline_k(2 * h + 1) == 1)
+        if (lanes_per_scanline_k(view_samples(h, G ? th.thin : 0)) == 1)
             scanline<1, G>(f.D, H, W, Mv, tv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, th, L, lane);
         else
             scanline<2, G>(f.D, H, W, Mv, tv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, th, L, lane);
@@ -1015,7 +1064,7 @@ ListLayout make_list_layout(int H, int W, int n_views, int edge_rows) {
 }
 
 void describe_frame(FrameDesc* f, const float* D, uint8_t* M, int H, int W, int n_views,
-                    const int* Ls, int edge_rows) {
+                    const int* Ls, int edge_rows, int thin) {
     f->D = D;
     f->M = M;
     f->H = H;
@@ -1038,7 +1087,7 @@ void describe_frame(FrameDesc* f, const float* D, uint8_t* M, int H, int W, int 
     for (int ci = 0; ci < kNumClasses; ++ci) {
         f->cls_start[ci] = k;
         for (int v = 0; v < n_views; ++v)
-            if (scan_class(f->h[v]) == ci) f->vord[k++] = v;
+            if (scan_class(f->h[v], thin) == ci) f->vord[k++] = v;
     }
     f->cls_start[kNumClasses] = k;
 }
@@ -1135,11 +1184,12 @@ hipError_t launch_scanlines_batched_g(hipStream_t st, const FrameDesc* table, in
 
 hipError_t launch_scanlines(hipStream_t st, const FrameDesc& f, int n_views, const ViewTable& vt,
                             const Thresholds& th, int cls, int n_blocks) {
-    return (th.bilinear || f.tstate || th.ns != 1) ? launch_scanlines_g<1>(st, f, n_views, vt, th, cls, n_blocks)
-                                                   : launch_scanlines_g<0>(st, f, n_views, vt, th, cls, n_blocks);
+    return (th.bilinear || th.thin || f.tstate || th.ns != 1)
+               ? launch_scanlines_g<1>(st, f, n_views, vt, th, cls, n_blocks)
+               : launch_scanlines_g<0>(st, f, n_views, vt, th, cls, n_blocks);
 }
 
-// Batched frames are never routed (no tile states).
+// Batched frames are never routed (no tile states) and never thinned.
 hipError_t launch_scanlines_batched(hipStream_t st, const FrameDesc* table, int n_frames,
                                     int n_views, const ViewTable& vt, const Thresholds& th,
                                     int cls, int n_blocks) {

@@ -330,6 +330,8 @@ occl_status occl_ctx::resolve_views(const float* D, int H, int W, int n_views,
     for (int v = 0; v < n_views; ++v) {
         if (Ls[v] < 1) return fail(OCCL_ERR_INVALID_ARG, "scan length < 1");
         if (Ls[v] > OCCL_MAX_SCAN_LEN) return fail(OCCL_ERR_UNSUPPORTED, "scan length > 1023");
+        if ((p->flags & OCCL_FLAG_THIN) && Ls[v] > OCCL_THIN_MAX_SCAN_LEN)
+            return fail(OCCL_ERR_UNSUPPORTED, "scan length > 683 with candidate thinning");
         direction_of(angles[v], &vt->c[v], &vt->s[v]);
         vt->r[v] = ratios[v];
     }
@@ -421,10 +423,10 @@ occl_status occl_ctx::enqueue_frame(const float* D, int H, int W, int n_views, c
                                     const TuneConfig* cfg, const uint8_t* tstate,
                                     const uint8_t* tnear) {
     int maxcls = 0;
-    for (int v = 0; v < n_views; ++v) maxcls = std::max(maxcls, scan_class(Ls[v] / 2));
+    for (int v = 0; v < n_views; ++v) maxcls = std::max(maxcls, scan_class(Ls[v] / 2, th.thin));
     const TuneConfig tc = cfg ? *cfg : config_for(tune_key(false, (size_t)H * W, n_views, maxcls));
     FrameDesc f;
-    describe_frame(&f, D, M, H, W, n_views, Ls, tc.edge_rows);
+    describe_frame(&f, D, M, H, W, n_views, Ls, tc.edge_rows, th.thin);
     void *lists, *counts, *prefix;
     occl_status s = ensure("lists", f.ll.cap * f.ll.copies * n_views * sizeof(uint32_t), &lists);
     if (s != OCCL_OK) return s;
@@ -509,6 +511,7 @@ Thresholds occl::make_thresholds(const occl_params* p) {
     int ns = (p->neighbours + 1) / 2;
     th.ns = ns < 1 ? 1 : ns;
     th.bilinear = (p->flags & OCCL_FLAG_BILINEAR) ? 1 : 0;
+    th.thin = (p->flags & OCCL_FLAG_THIN) ? 1 : 0;
     return th;
 }
 
@@ -530,6 +533,8 @@ occl_status detect_impl(occl_ctx* ctx, const float* D, int32_t H, int32_t W, int
     if (routed && !logits) return ctx->fail(OCCL_ERR_INVALID_ARG, "logits is NULL");
     if (H > 65535 || W > 65535) return ctx->fail(OCCL_ERR_UNSUPPORTED, "frame too large");
     const bool cnn = !routed && (params->flags & OCCL_FLAG_USE_CNN);
+    if ((params->flags & OCCL_FLAG_THIN) && (routed || cnn))
+        return ctx->fail(OCCL_ERR_UNSUPPORTED, "candidate thinning with routed tiles");
     if (cnn && !ctx->cnn_ready()) return ctx->fail(OCCL_ERR_NO_MODEL, "USE_CNN without loaded weights");
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return ctx->hip_fail(e, "hipSetDevice");

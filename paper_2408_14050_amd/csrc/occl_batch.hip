@@ -175,6 +175,7 @@ occl_status prepare_batch(occl_ctx* ctx, int32_t n_frames, const occl_frame* fra
     occl_status s = ctx->check_params(params, n_views, angles_deg, ratios);
     if (s != OCCL_OK) return s;
     if (params->flags & OCCL_FLAG_USE_CNN) return ctx->fail(OCCL_ERR_UNSUPPORTED, "USE_CNN in a batch");
+    if (params->flags & OCCL_FLAG_THIN) return ctx->fail(OCCL_ERR_UNSUPPORTED, "candidate thinning in a batch");
     for (int f = 0; f < n_frames; ++f) {
         const occl_frame& fr = frames[f];
         if (fr.H < 0 || fr.W < 0) return ctx->fail(OCCL_ERR_INVALID_ARG, "negative frame size");
@@ -319,7 +320,7 @@ extern "C" occl_status occl_autotune(occl_ctx* ctx, const float* D, int32_t H, i
                reps > 0 ? reps : 10, &best, &best_ms);
     if (s != OCCL_OK) return s;
     int maxcls = 0;
-    for (int v = 0; v < n_views; ++v) maxcls = std::max(maxcls, scan_class(Ls[v] / 2));
+    for (int v = 0; v < n_views; ++v) maxcls = std::max(maxcls, scan_class(Ls[v] / 2, th.thin));
     ctx->tuned[tune_key(false, (size_t)H * W, n_views, maxcls)] = best;
     if (out) {
         out->edge_rows = best.edge_rows;

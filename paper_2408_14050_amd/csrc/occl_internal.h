@@ -49,10 +49,15 @@ __host__ __device__ inline int lanes_per_scanline_k(int n) {
     while (64 * k < n) k <<= 1;
     return k;
 }
-__host__ __device__ inline int scan_class(int h) {
-    const int K = lanes_per_scanline_k(2 * h + 1);
+// Class of a scanline of at most n samples.
+__host__ __device__ inline int scan_class_n(int n) {
+    const int K = lanes_per_scanline_k(n);
     return K <= 2 ? 0 : (K == 4 ? 1 : (K == 8 ? 2 : 3));
 }
+// Longest scanline of a view with half length h: 2h + 1 samples, 3h + 1
+// with candidate thinning (a merged window reaches h further).
+__host__ __device__ inline int view_samples(int h, int thin) { return thin ? 3 * h + 1 : 2 * h + 1; }
+__host__ __device__ inline int scan_class(int h, int thin = 0) { return scan_class_n(view_samples(h, thin)); }
 
 // Per-view constants shared by every frame of a call, passed by value as a
 // kernel argument (copied at launch, so nothing on the host has to outlive
@@ -70,6 +75,7 @@ struct Thresholds {
     float zeta;    // distance threshold (Eq. 5)
     int ns;        // neighbours per side, max(1, ceil(N/2))
     int bilinear;  // 1: V by bilinear interpolation at the real sample position (variant)
+    int thin;      // 1: candidate thinning (variant; single frames, not routed)
 };
 
 struct ListLayout {
@@ -120,7 +126,7 @@ struct TuneConfig {
 // Fills the fields of a FrameDesc that depend only on sizes and scan lengths
 // (layout, grid, class order); the workspace pointers are set by the caller.
 void describe_frame(FrameDesc* f, const float* D, uint8_t* M, int H, int W, int n_views,
-                    const int* Ls, int edge_rows);
+                    const int* Ls, int edge_rows, int thin = 0);
 
 // ---- launchers (k_exact.hip) ------------------------------------------------
 hipError_t launch_edges(hipStream_t st, const FrameDesc& f, int n_views, const ViewTable& vt,

@@ -25,6 +25,7 @@ FLAG_SYNC = 1
 FLAG_VALIDATE_INPUT = 2
 FLAG_USE_CNN = 4
 FLAG_BILINEAR = 8
+FLAG_THIN = 16
 
 
 class OcclError(RuntimeError):
