@@ -539,17 +539,14 @@ __device__ __forceinline__ int thin_window(const float* __restrict__ D, int H, i
     return 2 * h + 1 + m;  // offsets t > h are never candidates, so m <= h
 }
 
+// One scanline: the n <= 64 K samples of offsets g = -h .. n - 1 - h
+// (n = 2h + 1, or a thinning head's merged window).
 template <int K, int G>
 __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int W,
                                          uint8_t* __restrict__ Mv, TileView tv, int cx, int cy, float c,
-                                         float s, float r, int h, const Thresholds& th,
+                                         float s, float r, int h, int n, const Thresholds& th,
                                          const WaveLds& L, int lane) {
     constexpr int N = 64 * K;
-    int n = 2 * h + 1;  // samples of the window g = -h .. n - 1 - h
-    if (G && th.thin) {
-        n = thin_window(D, H, W, cx, cy, c, s, h, th.q_min, lane);
-        if (n == 0) return;  // uniform: a follower is not scanned
-    }
     float wk[K], vk[K];  // this lane's W and V of slot k
     uint64_t vmask[K];
     bool kept[K];  // this lane's sample of slot k is in the frame (the bit of vmask[k])
@@ -797,13 +794,20 @@ __device__ __forceinline__ void scan_item(const FrameDesc& f, int v, uint32_t pi
     uint8_t* Mv = f.M + (size_t)v * H * W;
     TileView tv{nullptr, f.tiles_x};
     if (G && f.tstate) tv.t = f.tstate + (size_t)v * ((H + kTile - 1) / kTile) * f.tiles_x;
+    int n = 2 * h + 1;
+    if (G && th.thin) {
+        n = thin_window(f.D, H, W, cx, cy, vt.c[v], vt.s[v], h, th.q_min, lane);
+        if (n == 0) return;  // uniform: a follower is not scanned
+    }
+    // the register class holds the view's longest window; a shorter one
+    // (most merged windows) takes the smaller K
     if constexpr (KMAX == 2) {
-        if (lanes_per_scanline_k(view_samples(h, G ? th.thin : 0)) == 1)
-            scanline<1, G>(f.D, H, W, Mv, tv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, th, L, lane);
+        if (n <= 64)
+            scanline<1, G>(f.D, H, W, Mv, tv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, n, th, L, lane);
         else
-            scanline<2, G>(f.D, H, W, Mv, tv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, th, L, lane);
+            scanline<2, G>(f.D, H, W, Mv, tv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, n, th, L, lane);
     } else {
-        scanline<KMAX, G>(f.D, H, W, Mv, tv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, th, L, lane);
+        scanline<KMAX, G>(f.D, H, W, Mv, tv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, n, th, L, lane);
     }
 }
 
