@@ -55,11 +55,13 @@ def test_thin_ragged_parity(gctx, torch, ref, shape, variant):
     np.testing.assert_array_equal(nc, nc_ref)
 
 
-@pytest.mark.parametrize("L", [3, 64, 129, 683])
+@pytest.mark.parametrize("L", [1, 3, 43, 63, 64, 129, 683])
 def test_thin_longest_runs(gctx, torch, ref, L):
     """Ramps whose every pixel is a candidate: one head per row scans
     3 floor(L/2) + 1 samples (1024 at the largest L) and every other
-    candidate is a follower."""
+    candidate is a follower.  L = 43 fills one 64-sample slot exactly; at
+    L = 63 the merged window (94) outgrows the first attempt's slot and runs
+    again with two; L = 1 decides followers outside its one-sample window."""
     H, W = 6, 700
     x = np.arange(W, dtype=np.float32)
     up = np.broadcast_to(np.float32(1.5) * x, (H, W)).copy()
