@@ -94,3 +94,31 @@ def test_thin_rejections(gctx, torch):
     assert e.value.status == UNSUPPORTED
     out = gctx.occl_detect(D, [0], [1.0], occl.params(scan_len=683, flags=thin))
     assert int(out.sum().item()) == 0
+
+
+def test_thin_autotuned_shape(gctx, torch, ref):
+    """The single-frame autotuner accepts the flag (its trial launches run the
+    thinned path) and the tuned shape gives the same bit-exact masks."""
+    from paper_2408_14050_amd import occl
+    sc = scenes.make_c1_like(5, W=640, H=480, n_objects=12, dmax=24.0)
+    angles, ratios, L = [0, 45, 200, 300], np.float32([1.0, 1.4142135, 1.2, 0.9]), [31, 41, 35, 27]
+    D = torch.from_numpy(sc.D).cuda()
+    M = torch.empty((4,) + sc.D.shape, dtype=torch.uint8, device="cuda")
+    prm = occl.params(scan_len_per_view=L, flags=occl.FLAG_SYNC | occl.FLAG_THIN)
+    shape = gctx.occl_autotune(D, angles, ratios, prm, M, reps=3)
+    assert shape["edge_rows"] > 0 and shape["scan_blocks_per_cu"] > 0
+    M_ref, _, _ = ref.detect(sc.D, angles, ratios, L, thin=True)
+    assert_parity(M.cpu().numpy(), M_ref, what="masks left by the autotuner")
+    M2, _ = _thin_gpu(gctx, torch, sc.D, angles, ratios, L)
+    assert_parity(M2, M_ref, what="tuned shape")
+
+
+def test_thin_large_frame_split_over_dies(gctx, torch, ref):
+    """A frame of >= 16 MB takes the scanline pass's per-die split; the
+    thinning decision rides along unchanged."""
+    sc = scenes.make_c1_like(7, W=2048, H=2100, n_objects=30, dmax=40.0)
+    angles, ratios, L = [0, 135], np.float32([1.0, 1.4142135]), [45, 61]
+    M_ref, _, nc_ref = ref.detect(sc.D, angles, ratios, L, thin=True)
+    M, nc = _thin_gpu(gctx, torch, sc.D, angles, ratios, L)
+    assert_parity(M, M_ref, what="thin 2100x2048")
+    np.testing.assert_array_equal(nc, nc_ref)
