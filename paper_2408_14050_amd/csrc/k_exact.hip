@@ -783,10 +783,12 @@ template <int KMAX>
 constexpr int batched_waves_per_block() { return KMAX <= 4 ? 8 : waves_per_block<KMAX>(); }
 
 // The scanline of candidate `pix` of view v of frame f.
+// run_check (thinning only): false when the caller has found the candidate
+// to be a head with no candidate at g = +1, whose window is the plain one.
 template <int KMAX, int G>
 __device__ __forceinline__ void scan_item(const FrameDesc& f, int v, uint32_t pix,
                                           const ViewTable& vt, const Thresholds& th,
-                                          const WaveLds& L, int lane) {
+                                          const WaveLds& L, int lane, bool run_check = true) {
     const int W = f.W, H = f.H;
     const int cy = (int)(pix >> 16);  // list entries are packed (y << 16) | x
     const int cx = (int)(pix & 0xffffu);
@@ -795,7 +797,7 @@ __device__ __forceinline__ void scan_item(const FrameDesc& f, int v, uint32_t pi
     TileView tv{nullptr, f.tiles_x};
     if (G && f.tstate) tv.t = f.tstate + (size_t)v * ((H + kTile - 1) / kTile) * f.tiles_x;
     int n = 2 * h + 1;
-    if (G && th.thin) {
+    if (G && th.thin && run_check) {
         n = thin_window(f.D, H, W, cx, cy, vt.c[v], vt.s[v], h, th.q_min, lane);
         if (n == 0) return;  // uniform: a follower is not scanned
     }
@@ -850,12 +852,29 @@ __global__ __launch_bounds__(64 * waves_per_block<KMAX>(), min_waves_per_simd<KM
     constexpr int NA = lds_arrays<KMAX>();
     const WaveLds L{lds[wave][0], okeys[wave], lds[wave][NA - 1], runs[wave]};
     // one item: the class-list index t, its segment found by stepping forward from lo
-    auto item = [&](int t, int& lo) {
+    auto item = [&](int t, int& lo, bool run_check) {
         while (lo + 1 < nseg && pre[lo + 1] <= t) ++lo;
         const int sv = segvs[lo];
         const int v = sv >> 16, seg = sv & 0xffff;
         const uint32_t pix = f.lists[(size_t)seg * f.ll.cap + (size_t)(t - pre[lo])];
-        scan_item<KMAX, G>(f, v, pix, vt, th, L, lane);
+        scan_item<KMAX, G>(f, v, pix, vt, th, L, lane, run_check);
+    };
+    // Thinning: one load round tests the pixels at g = -1 (lane 2i) and
+    // g = +1 (lane 2i + 1) of item g0 + i of a group.  Bit 2i of the result:
+    // the item is a follower; bit 2i + 1: it has a candidate at g = +1.
+    auto thin_group = [&](int g0, int g1, int lo) {
+        bool is_c = false;
+        if (lane < 2 * (g1 - g0)) {
+            const int t = g0 + (lane >> 1);
+            int l = lo;
+            while (l + 1 < nseg && pre[l + 1] <= t) ++l;
+            const int sv = segvs[l];
+            const int v = sv >> 16, seg = sv & 0xffff;
+            const uint32_t pix = f.lists[(size_t)seg * f.ll.cap + (size_t)(t - pre[l])];
+            is_c = candidate_at(f.D, f.H, f.W, (int)(pix & 0xffffu), (int)(pix >> 16), vt.c[v], vt.s[v],
+                                (lane & 1) ? 1 : -1, th.q_min);
+        }
+        return (uint32_t)__ballot(is_c);
     };
     auto seg_of = [&](int t) {  // last segment with pre <= t
         int lo = 0, hi = nseg - 1;
@@ -887,7 +906,15 @@ __global__ __launch_bounds__(64 * waves_per_block<KMAX>(), min_waves_per_simd<KM
         for (int g0 = gw * kGroup; g0 < total; g0 += nw * kGroup) {
             const int g1 = min(total, g0 + kGroup);
             int lo = seg_of(g0);
-            for (int t = g0; t < g1; ++t) item(t, lo);
+            if (G && th.thin) {
+                const uint32_t tb = thin_group(g0, g1, lo);
+                for (int t = g0; t < g1; ++t) {
+                    const uint32_t b = tb >> (2 * (t - g0));
+                    if (!(b & 1u)) item(t, lo, (b & 2u) != 0);  // followers are skipped
+                }
+            } else {
+                for (int t = g0; t < g1; ++t) item(t, lo, true);
+            }
         }
         return;
     }
@@ -930,7 +957,7 @@ __global__ __launch_bounds__(64 * waves_per_block<KMAX>(), min_waves_per_simd<KM
         int lo = seg_of(gst[j] + (g0 - dst[j]));
         for (int tl = g0; tl < g1; ++tl) {
             while (j + 1 < nvc && dst[j + 1] <= tl) ++j;
-            item(gst[j] + (tl - dst[j]), lo);
+            item(gst[j] + (tl - dst[j]), lo, true);
         }
     }
 }
