@@ -141,7 +141,7 @@ def cpu_baseline(sc, seconds: float):
 
 
 # ---------------------------------------------------------------------------
-# profiling helpers (run under rocprofv3 on the GPU machine, summarised here)
+# profiling helpers (run under rocprofv3 on the GPU, summarised here)
 # ---------------------------------------------------------------------------
 PROFILE_CMD = ("rocprofv3 {mode} -d gpurun_out/{out} -o run -- python3 bench.py --steps 20 "
                "--warmup 2 --prewarm 0 --streams 1 --no-cpu-baseline --no-context --no-check "
@@ -251,7 +251,7 @@ def profiles_from(run_dir: str, workload: str) -> int:
             lines = [
                 f"# {k} -- {wl}",
                 "",
-                "Commands (from the repository root on the GPU box):",
+                "Commands (from the repository root):",
                 "  " + cmd.format(mode="--kernel-trace --stats", out=pre + "prof"),
                 "  " + cmd.format(mode="--pmc FETCH_SIZE", out=pre + "pmc_fetch"),
                 "  " + cmd.format(mode="--pmc WRITE_SIZE", out=pre + "pmc_write"),
@@ -557,7 +557,7 @@ def main() -> int:
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the detector's "
-              "sharding across GPUs is described in DESIGN.md but not built", file=sys.stderr)
+              "sharding across GPUs is not built", file=sys.stderr)
         return 2
 
     import numpy as np

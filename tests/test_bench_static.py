@@ -1,6 +1,6 @@
 """Static checks of bench.py and __graft_entry__.py on the CPU: every name
 they call is defined, imported or a builtin (a missing helper would only
-show up on the GPU machine), and the multi-GPU request exits with its message."""
+show up on a GPU run), and the multi-GPU request exits with its message."""
 import ast
 import builtins
 import os
