@@ -148,11 +148,14 @@ PROFILE_CMD = ("rocprofv3 {mode} -d gpurun_out/{out} -o run -- python3 bench.py 
                "--no-learned --no-quality")
 QUALITY_PROFILE_CMD = ("rocprofv3 {mode} -d gpurun_out/{out} -o run -- python3 bench.py "
                        "--quality-only")
+THIN_PROFILE_CMD = "rocprofv3 {mode} -d gpurun_out/{out} -o run -- python3 bench.py --thin-only"
 LEARNED_PROFILE_CMD = ("rocprofv3 {mode} -d gpurun_out/{out} -o run -- python3 bench.py --learned-only "
                        "--learned-steps 10 --learned-eval 1")
 BATCH_WORKLOAD = "c3 64 mixed frames seed 3000"
 QUALITY_WORKLOAD = "c1 1280x960 x8 views seeds 1000-1003"
 LEARNED_WORKLOAD = "c4 1920x1080 x8 views seed 4100"
+THIN_WORKLOAD = "c1 1280x960 x8 views seed 1002 thinned"
+THIN_KERNELS = ("k_scanlines<2, 1>",)
 LEARNED_KERNELS = ("k_pack", "k_conv", "k_route")
 QUALITY_KERNELS = ("k_zbuf", "k_fill", "k_median", "k_confusion", "k_stats")
 COPY_CMD = "rocprofv3 --pmc {ctr} -d gpurun_out/{out} -o run -- python3 bench.py --copy-probe 256"
@@ -210,8 +213,8 @@ def profiles_from(run_dir: str, workload: str) -> int:
     """Writes profiles/<kernel>__<workload>.txt and profiles/traffic.json from
     the rocprofv3 databases of the profiling runs: trace, FETCH_SIZE and
     WRITE_SIZE passes of the benchmark (prof, pmc_fetch, pmc_write), of its
-    learned section (lprof, lpmc_fetch, lpmc_write; optional) and of the
-    copy probe (copy_fetch, copy_write)."""
+    learned, quality and thinning sections (l-, q- and t-prefixed; optional)
+    and of the copy probe (copy_fetch, copy_write)."""
     import glob
     def db(sub):
         g = glob.glob(os.path.join(run_dir, sub, "*.db"))
@@ -227,7 +230,8 @@ def profiles_from(run_dir: str, workload: str) -> int:
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     runs = [("", PROFILE_CMD, lambda k: not k.startswith(LEARNED_KERNELS + QUALITY_KERNELS)),
             ("l", LEARNED_PROFILE_CMD, lambda k: k.startswith(LEARNED_KERNELS)),
-            ("q", QUALITY_PROFILE_CMD, lambda k: k.startswith(QUALITY_KERNELS))]
+            ("q", QUALITY_PROFILE_CMD, lambda k: k.startswith(QUALITY_KERNELS)),
+            ("t", THIN_PROFILE_CMD, lambda k: k.startswith(THIN_KERNELS))]
     for pre, cmd, keep in runs:
         if not db(pre + "prof"):
             continue
@@ -239,6 +243,8 @@ def profiles_from(run_dir: str, workload: str) -> int:
                 wl = LEARNED_WORKLOAD
             elif pre == "q":
                 wl = QUALITY_WORKLOAD
+            elif pre == "t":
+                wl = THIN_WORKLOAD
             else:
                 wl = BATCH_WORKLOAD if "batched" in k else workload
             tag = wl.split(":")[0].replace(" ", "_").replace("x8_views", "v8")
@@ -543,6 +549,7 @@ def main() -> int:
     ap.add_argument("--learned-only", action="store_true", help="only the learned-path section")
     ap.add_argument("--no-quality", action="store_true")
     ap.add_argument("--quality-only", action="store_true", help="only the quality and fusion sections")
+    ap.add_argument("--thin-only", action="store_true", help="only the candidate-thinning section")
     ap.add_argument("--streams", type=int, default=3,
                     help="frames in flight: contexts on separate HIP streams, steps round-robin")
     ap.add_argument("--prewarm", type=int, default=PREWARM_STEPS,
@@ -570,6 +577,11 @@ def main() -> int:
     if args.learned_only:
         ctx = occl.Context(0)
         print(json.dumps(bench_learned(ctx, args.learned_steps, args.learned_eval)), flush=True)
+        ctx.occl_release()
+        return 0
+    if args.thin_only:
+        ctx = occl.Context(0)
+        print(json.dumps({"thinning": bench_thin(ctx, args.seed)}), flush=True)
         ctx.occl_release()
         return 0
     if args.quality_only:
