@@ -122,3 +122,17 @@ def test_thin_large_frame_split_over_dies(gctx, torch, ref):
     M, nc = _thin_gpu(gctx, torch, sc.D, angles, ratios, L)
     assert_parity(M, M_ref, what="thin 2100x2048")
     np.testing.assert_array_equal(nc, nc_ref)
+
+
+def test_thin_eq3_scan_length(gctx, torch, ref):
+    """Eq. (3)'s L read from D on the device (scan_len = -1): longer windows,
+    larger register classes, thinned."""
+    from paper_2408_14050_amd import occl
+    sc = scenes.make_scene("c1", 1001)
+    Ls = ref.scan_len(sc.D, sc.ratios, -1)
+    assert Ls.max() <= 683
+    M_ref, _, _ = ref.detect(sc.D, sc.angles, sc.ratios, Ls, thin=True)
+    D = torch.from_numpy(sc.D).cuda()
+    M = gctx.occl_detect(D, sc.angles, sc.ratios,
+                         occl.params(**sc.params, scan_len=-1, flags=occl.FLAG_SYNC | occl.FLAG_THIN))
+    assert_parity(M.cpu().numpy(), M_ref, what=f"thin Eq. (3) L {Ls.tolist()}")
