@@ -108,7 +108,8 @@ void occl_params_default(occl_params* p);
 
 /* Creates a context on HIP device `device`.  `hip_stream` is the hipStream_t
  * every call of this context is enqueued on (NULL: the device's default
- * stream).  The library never creates or destroys streams.  The hints size
+ * stream).  All work is enqueued on that stream; the library's own two
+ * streams serve only to capture the batched launch's graph.  The hints size
  * the initial workspace (0: grow on first use). */
 occl_status occl_init(occl_ctx** out, int device, void* hip_stream, size_t max_pixels_hint,
                       int32_t max_views_hint);

@@ -120,6 +120,9 @@ occl_ctx::~occl_ctx() {
     if (table_event) (void)hipEventDestroy(table_event);
     if (table_host) (void)hipHostFree(table_host);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (cap_stream2) (void)hipStreamDestroy(cap_stream2);
+    if (cap_fork) (void)hipEventDestroy(cap_fork);
+    if (cap_join) (void)hipEventDestroy(cap_join);
     free_all();
     if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
