@@ -120,9 +120,11 @@ occl_ctx::~occl_ctx() {
     if (table_event) (void)hipEventDestroy(table_event);
     if (table_host) (void)hipHostFree(table_host);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
-    if (cap_stream2) (void)hipStreamDestroy(cap_stream2);
+    for (auto& st : cap_extra)
+        if (st) (void)hipStreamDestroy(st);
     if (cap_fork) (void)hipEventDestroy(cap_fork);
-    if (cap_join) (void)hipEventDestroy(cap_join);
+    for (auto& ev : cap_join)
+        if (ev) (void)hipEventDestroy(ev);
     free_all();
     if (own_stream && stream) (void)hipStreamDestroy(stream);
 }

@@ -28,8 +28,10 @@ namespace {
 struct BatchSig {
     const void* table;
     int n_frames, total_blocks, n_views, edge_rows, edge_grid, scan_grid;
-    int n_first, blocks_first;  // the first branch's frames and edge blocks
-    unsigned cls_mask, cls_mask_second;
+    int n_branches;
+    int cut[kMaxBatchBranches + 1];     // branch b holds frames cut[b] .. cut[b + 1] - 1
+    int bstart[kMaxBatchBranches + 1];  // ... and flat edge blocks bstart[b] .. bstart[b + 1] - 1
+    unsigned cls_mask[kMaxBatchBranches];
     Thresholds th;
     ViewTable vt;
 };
@@ -65,40 +67,43 @@ occl_status occl_ctx::enqueue_batch(int n_frames, const occl_frame* frames, int 
         e = hipEventSynchronize(table_event);  // the previous upload has left the staging area
         if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize(table)");
     }
-    // Two branches: the frames up to half the batch's pixels, and the rest,
-    // each with its own edge pass and scanline pass, run side by side by the
-    // graph (c3: 1.74-1.79 -> 1.66 ms; the second branch's edge pass chained
-    // after the first's, to run beside the first's scanline pass, measured
-    // 1.73 ms).  Each branch's blocks are numbered from 0.
-    int n_first = n_frames;
-    if (n_frames >= 2) {
+    // Branches: consecutive frames of about equal pixel counts, each with its
+    // own edge pass and scanline pass, run side by side by the graph (c3,
+    // two branches: 1.74-1.79 -> 1.65-1.66 ms; three 1.69 ms, four 1.70-1.73;
+    // the second branch's edge pass chained after the first's, to run beside
+    // the first's scanline pass, 1.73 ms).  Each branch's blocks are numbered
+    // from 0.
+    const int nb = std::max(1, std::min(kBatchBranches, n_frames));
+    int cut[kMaxBatchBranches + 1] = {};
+    cut[nb] = n_frames;
+    {
         size_t acc = 0;
-        for (int f = 0; f < n_frames; ++f) {
+        int b = 1;
+        for (int f = 0; f < n_frames && b < nb; ++f) {
             acc += (size_t)frames[f].H * frames[f].W;
-            if (2 * acc >= px) {
-                n_first = f + 1;
-                break;
-            }
+            while (b < nb && acc * nb >= px * b) cut[b++] = f + 1;
         }
-        n_first = std::min(n_first, n_frames - 1);
+        for (b = 1; b < nb; ++b)  // every branch keeps at least one frame
+            cut[b] = std::min(std::max(cut[b], cut[b - 1] + 1), n_frames - (nb - b));
     }
     size_t lists_total = 0;
-    int total_blocks = 0, blocks_first = 0;
-    unsigned cls_mask = 0, cls_mask_second = 0;
+    int total_blocks = 0;
+    int bstart[kMaxBatchBranches + 1] = {};
+    unsigned cls_mask[kMaxBatchBranches] = {};
     std::vector<size_t> lists_off(n_frames);
-    for (int f = 0; f < n_frames; ++f) {
+    for (int f = 0, b = 0; f < n_frames; ++f) {
+        while (f == cut[b + 1]) bstart[++b] = total_blocks;
         FrameDesc& d = table_host[f];
         describe_frame(&d, frames[f].D, frames[f].M, frames[f].H, frames[f].W, n_views,
                        Ls_all + (size_t)f * n_views, tc.edge_rows);
-        if (f == n_first) blocks_first = total_blocks;
-        d.block_begin = total_blocks - (f >= n_first ? blocks_first : 0);
+        d.block_begin = total_blocks - bstart[b];
         total_blocks += d.gx * d.gy;
         lists_off[f] = lists_total;
         lists_total += d.ll.cap * d.ll.copies * n_views;
         for (int ci = 0; ci < kNumClasses; ++ci)
-            if (d.cls_start[ci + 1] > d.cls_start[ci]) (f < n_first ? cls_mask : cls_mask_second) |= 1u << ci;
+            if (d.cls_start[ci + 1] > d.cls_start[ci]) cls_mask[b] |= 1u << ci;
     }
-    if (n_first == n_frames) blocks_first = total_blocks;
+    bstart[nb] = total_blocks;
     void *lists, *counts, *prefix, *table;
     occl_status s = ensure("blists", std::max<size_t>(lists_total, 1) * sizeof(uint32_t), &lists);
     if (s == OCCL_OK) s = ensure_zeroed("bcounts", (size_t)n_frames * kCountsBytes, &counts);
@@ -125,10 +130,12 @@ occl_status occl_ctx::enqueue_batch(int n_frames, const occl_frame* frames, int 
     sg.edge_rows = tc.edge_rows;
     sg.edge_grid = n_cu * edges_batched_blocks_per_cu(tc.edge_rows);
     sg.scan_grid = tc.scan_blocks_per_cu * n_cu;
-    sg.n_first = n_first;
-    sg.blocks_first = blocks_first;
-    sg.cls_mask = cls_mask;
-    sg.cls_mask_second = cls_mask_second;
+    sg.n_branches = nb;
+    for (int b = 0; b <= nb; ++b) {
+        sg.cut[b] = cut[b];
+        sg.bstart[b] = bstart[b];
+        if (b < nb) sg.cls_mask[b] = cls_mask[b];
+    }
     sg.th = th;
     sg.vt = vt;
     const std::vector<uint8_t> key = sig_bytes(sg);
@@ -141,7 +148,6 @@ occl_status occl_ctx::enqueue_batch(int n_frames, const occl_frame* frames, int 
         }
     }
     if (!exec) {
-        const bool split = n_first < n_frames;
         if (!cap_stream) {
             e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
             if (e != hipSuccess) {
@@ -149,33 +155,49 @@ occl_status occl_ctx::enqueue_batch(int n_frames, const occl_frame* frames, int 
                 return hip_fail(e, "hipStreamCreate(capture)");
             }
         }
-        if (split && !cap_stream2) {
-            e = hipStreamCreateWithFlags(&cap_stream2, hipStreamNonBlocking);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&cap_fork, hipEventDisableTiming);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&cap_join, hipEventDisableTiming);
-            if (e != hipSuccess) return hip_fail(e, "batch branch stream");
+        if (nb > 1 && !cap_fork) {
+            e = hipEventCreateWithFlags(&cap_fork, hipEventDisableTiming);
+            if (e != hipSuccess) {
+                cap_fork = nullptr;
+                return hip_fail(e, "hipEventCreate(fork)");
+            }
+        }
+        for (int b = 1; b < nb; ++b) {
+            if (!cap_extra[b - 1]) {
+                e = hipStreamCreateWithFlags(&cap_extra[b - 1], hipStreamNonBlocking);
+                if (e != hipSuccess) {
+                    cap_extra[b - 1] = nullptr;
+                    return hip_fail(e, "hipStreamCreate(branch)");
+                }
+            }
+            if (!cap_join[b - 1]) {
+                e = hipEventCreateWithFlags(&cap_join[b - 1], hipEventDisableTiming);
+                if (e != hipSuccess) {
+                    cap_join[b - 1] = nullptr;
+                    return hip_fail(e, "hipEventCreate(join)");
+                }
+            }
         }
         e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
         // one branch: the edge pass, then the scanline pass of each class present
-        auto branch = [&](hipStream_t st, const FrameDesc* t, int nf, int blocks, unsigned mask) {
+        auto branch = [&](hipStream_t st, int b) {
+            const FrameDesc* t = (const FrameDesc*)table + cut[b];
+            const int nf = cut[b + 1] - cut[b], blocks = bstart[b + 1] - bstart[b];
             hipError_t r = launch_edges_batched(st, t, nf, blocks, n_views, vt, th.q_min, tc.edge_rows,
                                                 std::min(blocks, sg.edge_grid));
             for (int ci = 0; ci < kNumClasses && r == hipSuccess; ++ci)
-                if (mask & (1u << ci)) r = launch_scanlines_batched(st, t, nf, n_views, vt, th, ci, sg.scan_grid);
+                if (cls_mask[b] & (1u << ci)) r = launch_scanlines_batched(st, t, nf, n_views, vt, th, ci, sg.scan_grid);
             return r;
         };
         hipError_t le = hipSuccess;
-        if (split) {
-            le = hipEventRecord(cap_fork, cap_stream);
-            if (le == hipSuccess) le = hipStreamWaitEvent(cap_stream2, cap_fork, 0);
-        }
-        if (le == hipSuccess) le = branch(cap_stream, (const FrameDesc*)table, n_first, blocks_first, cls_mask);
-        if (split && le == hipSuccess) {
-            le = branch(cap_stream2, (const FrameDesc*)table + n_first, n_frames - n_first,
-                        total_blocks - blocks_first, cls_mask_second);
-            if (le == hipSuccess) le = hipEventRecord(cap_join, cap_stream2);
-            if (le == hipSuccess) le = hipStreamWaitEvent(cap_stream, cap_join, 0);
+        if (nb > 1) le = hipEventRecord(cap_fork, cap_stream);
+        for (int b = 1; b < nb && le == hipSuccess; ++b) le = hipStreamWaitEvent(cap_extra[b - 1], cap_fork, 0);
+        if (le == hipSuccess) le = branch(cap_stream, 0);
+        for (int b = 1; b < nb && le == hipSuccess; ++b) {
+            le = branch(cap_extra[b - 1], b);
+            if (le == hipSuccess) le = hipEventRecord(cap_join[b - 1], cap_extra[b - 1]);
+            if (le == hipSuccess) le = hipStreamWaitEvent(cap_stream, cap_join[b - 1], 0);
         }
         hipGraph_t graph = nullptr;
         e = hipStreamEndCapture(cap_stream, &graph);

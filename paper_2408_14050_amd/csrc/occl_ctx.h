@@ -52,8 +52,9 @@ struct occl_ctx {
     occl::FrameDesc* table_host = nullptr;  // pinned, kMaxBatch entries
     hipEvent_t table_event = nullptr;       // last upload from table_host
     hipStream_t cap_stream = nullptr;       // graphs are captured here (never the null stream)
-    hipStream_t cap_stream2 = nullptr;      // second branch of a batch graph (capture only)
-    hipEvent_t cap_fork = nullptr, cap_join = nullptr;  // the batch graph's fork and join
+    hipStream_t cap_extra[occl::kMaxBatchBranches - 1] = {};  // further branches of a batch graph (capture only)
+    hipEvent_t cap_fork = nullptr;                       // the batch graph's fork ...
+    hipEvent_t cap_join[occl::kMaxBatchBranches - 1] = {};    // ... and joins
     struct GraphEntry {
         std::vector<uint8_t> sig;
         hipGraph_t graph = nullptr;

@@ -42,6 +42,13 @@ constexpr size_t kPrefixInts = kMaxSegments + 1;
 // 16 samples per lane; class 0 serves K = 1 and 2, classes 1..3 serve 4, 8, 16.
 constexpr int kNumClasses = 4;
 constexpr int kMaxBatch = 1024;
+// Graph branches of a batched launch (frames split by pixel count).
+#ifndef OCCL_BATCH_BRANCHES
+#define OCCL_BATCH_BRANCHES 2
+#endif
+constexpr int kMaxBatchBranches = 4;
+constexpr int kBatchBranches = OCCL_BATCH_BRANCHES;
+static_assert(kBatchBranches >= 1 && kBatchBranches <= kMaxBatchBranches, "batch branches");
 
 // Smallest K (power of two, 1..16) with 64*K >= n samples.
 __host__ __device__ inline int lanes_per_scanline_k(int n) {
