@@ -157,3 +157,18 @@ def test_extreme_extents_in_one_batch(gctx, torch, ref):
     for f, M in zip(frames, Ms):
         np.testing.assert_array_equal(M.cpu().numpy(), _ref(ref, f), err_msg=f.name)
 
+
+
+@pytest.mark.parametrize("sizes", [
+    ((640, 480),),                                    # one frame: one branch
+    ((320, 240), (640, 480)),                         # two frames: one per branch
+    ((1920, 1080), (64, 48), (32, 24), (16, 12)),     # the first frame holds most pixels
+    ((16, 12), (32, 24), (64, 48), (1920, 1080)),     # the last frame holds most pixels
+])
+def test_branch_split_edge_cases(gctx, torch, ref, sizes):
+    """The batch is split into graph branches of about equal pixel counts;
+    every branch keeps at least one frame whatever the size mix."""
+    frames = [scenes.make_c1_like(7400 + i, W=w, H=h) for i, (w, h) in enumerate(sizes)]
+    _, Ms = _run_batch(gctx, torch, frames)
+    for f, M in zip(frames, Ms):
+        assert np.array_equal(M.cpu().numpy(), _ref(ref, f)), f"{f.W}x{f.H}"
