@@ -14,7 +14,10 @@ checks use it; the GPU library never calls it):
 * the network: 6 layers (8->32 s2, 32->32 s2, 32->32 s2, 32->32 s2,
   32->32 s1, 32->1 s1), ReLU after all but the last; activations and
   activation gradients are rounded to bf16 between layers, logits and their
-  gradient stay fp32 -- the same storage precisions as the GPU kernels.
+  gradient stay fp32 -- the same storage precisions as the GPU kernels;
+* tile routing: a tile whose occlusion probability sigmoid(z) lies below the
+  band [lo, hi] is filled with 0, above it with 1, and otherwise takes the
+  exact path (a NaN logit too).
 """
 from __future__ import annotations
 
@@ -190,3 +193,27 @@ def tile_fraction(M, tile=TILE):
             blk = M[..., ty * tile:(ty + 1) * tile, tx * tile:(tx + 1) * tile]
             out[..., ty, tx] = blk.mean(axis=(-2, -1))
     return out
+
+
+def logit_bound(p):
+    """The logit of a probability bound, evaluated in double and rounded to
+    fp32 (p <= 0 -> -inf, p >= 1 -> +inf): sigmoid(z) < p  <=>  z < logit(p)
+    since the logistic function is strictly increasing."""
+    if p <= 0:
+        return np.float32(-np.inf)
+    if p >= 1:
+        return np.float32(np.inf)
+    return np.float32(np.log(p / (1.0 - p)))
+
+
+def tile_states(z, lo, hi):
+    """Routing state of every tile from its logit z (fp32): 0 (fill 0) if
+    z < logit(lo), 1 (fill 1) if z > logit(hi), else 2 (exact path); a NaN
+    logit compares false both ways and takes the exact path."""
+    z = np.asarray(z, np.float32)
+    zl, zh = logit_bound(lo), logit_bound(hi)
+    s = np.full(z.shape, 2, np.uint8)
+    s[z < zl] = 0
+    s[z > zh] = 1
+    return s
+

@@ -185,6 +185,17 @@ void sort_and_test(std::vector<Sample>& smp, float zeta, float beta, int ns,
     }
 }
 
+// Eq. (5) at sorted position k of an ordered scanline: O_k > 0.
+bool hit_at(const std::vector<Sample>& smp, int k, float zeta, float beta, int ns) {
+    const int n = (int)smp.size();
+    for (int d = -ns; d <= ns; ++d) {
+        const int j = k + d;
+        if (d == 0 || j < 0 || j >= n) continue;
+        if (std::fabs(smp[k].W - smp[j].W) < zeta && smp[j].V - smp[k].V > beta) return true;
+    }
+    return false;
+}
+
 // Pixel of scanline offset g of candidate (cx, cy) (Eq. (4), R5); false
 // when it falls outside the frame.
 bool scanline_pixel(int cx, int cy, float c, float s, int g, int H, int W, int* ix, int* iy) {
@@ -201,6 +212,49 @@ bool scanline_pixel(int cx, int cy, float c, float s, int g, int H, int W, int* 
 inline int neighbours_per_side(int N) {
     int ns = (N + 1) / 2;  // ceil(N/2)
     return ns < 1 ? 1 : ns;
+}
+
+// The tight map (parity exemption): the pixels whose mask value rests on a
+// decision taken within kTightEps of its threshold.  A margin that is
+// exactly 0 is not tight: it comes from exact operands (a zero factor,
+// integer offsets, equal disparities), every implementation that rounds
+// each operation as written decides it the same way, and the paper's
+// strict tests and the stable sort's tie rule decide it.
+//   (i)   Eq. (2): 0 < |dot| < eps for a strong edge, or dot == 0 as the sum
+//         of two non-zero products that cancel (a rounding artefact).  The
+//         magnitude test E > gamma is no margin: E and the comparison are
+//         fixed by the definition (correctly rounded square root).
+//   (ii)  Eq. (4): a scanline coordinate within eps of a half pixel (the
+//         exact half included: its tie rule is a reading).
+//   (iii) the sort: 0 < |W_a - W_b| < eps for sorted neighbours.
+//   (iv)  Eq. (5): 0 < |zeta - |dW|| < eps or 0 < |dV - beta| < eps in a
+//         comparison that could decide a hit.
+inline bool in_margin(float m) { return m != 0.0f && std::fabs(m) < kTightEps; }
+
+inline bool dot_margin_tight(float ex, float ey, float c, float s) {
+    float a = ex * c;
+    float b = ey * s;
+    float dot = a + b;
+    if (dot == 0.0f) return a != 0.0f && b != 0.0f;
+    return std::fabs(dot) < kTightEps;
+}
+
+// (iv) for sorted sample k: a comparison within eps of zeta or beta could
+// flip, and no comparison outside the margins already makes it a hit.
+bool decision_fragile(const std::vector<Sample>& smp, int k, float zeta, float beta, int ns) {
+    const int n = (int)smp.size();
+    bool near = false, robust_hit = false;
+    for (int d = -ns; d <= ns; ++d) {
+        const int j = k + d;
+        if (d == 0 || j < 0 || j >= n) continue;
+        const float dw = std::fabs(smp[k].W - smp[j].W);
+        const float dv = smp[j].V - smp[k].V;
+        const bool m = (in_margin(zeta - dw) && dv > beta - kTightEps) ||
+                       (in_margin(dv - beta) && dw < zeta + kTightEps);
+        if (m) near = true;
+        else if (dw < zeta && dv > beta) robust_hit = true;
+    }
+    return near && !robust_hit;
 }
 
 inline bool near_half(float p) {
@@ -401,6 +455,7 @@ int occl_ref_detect_ex(const float* D, int H, int W, int n_views, const double* 
     std::vector<Sample> smp;
     std::vector<unsigned char> hit;
     std::vector<unsigned char> candv(thin ? HW : 0);
+    std::vector<unsigned char> fragile_px, robust_px;
     for (int v = 0; v < n_views; ++v) {
         float c, s;
         ref_direction(angles[v], &c, &s);
@@ -408,6 +463,14 @@ int occl_ref_detect_ex(const float* D, int H, int W, int n_views, const double* 
         const int h = scan_len[v] / 2;
         unsigned char* Mv = M + HW * v;
         unsigned char* Tv = tight ? tight + HW * v : nullptr;
+        // tight bookkeeping: Fv = some sample of the pixel could flip its hit,
+        // Rv = some hit of the pixel is robust
+        if (Tv) {
+            fragile_px.assign(HW, 0);
+            robust_px.assign(HW, 0);
+        }
+        unsigned char* Fv = Tv ? fragile_px.data() : nullptr;
+        unsigned char* Rv = Tv ? robust_px.data() : nullptr;
         long long nc = 0;
         if (thin)  // Eq. (2) over the whole frame, for the follower / run tests
             for (size_t i = 0; i < HW; ++i)
@@ -417,11 +480,9 @@ int occl_ref_detect_ex(const float* D, int H, int W, int n_views, const double* 
                 size_t i = (size_t)y * W + x;
                 float dot = edge_dot(ex[i], ey[i], c, s);
                 bool cand = is_candidate(E[i], dot, gamma);  // Eq. (2)
-                bool cand_tight = false;
-                if (Tv) {
-                    cand_tight = (std::fabs(E[i] - gamma) < kTightEps && dot > -kTightEps) ||
-                                 (std::fabs(dot) < kTightEps && E[i] > gamma - kTightEps);
-                }
+                // tight (i): a strong edge whose direction test rests on a dot
+                // product within eps of 0 (the magnitude test is not a margin)
+                const bool cand_tight = Tv && E[i] > gamma && dot_margin_tight(ex[i], ey[i], c, s);
                 if (!cand && !cand_tight) continue;
                 int hi = h;
                 if (thin) {
@@ -437,50 +498,51 @@ int occl_ref_detect_ex(const float* D, int H, int W, int n_views, const double* 
                     hi = h + m;
                 }
                 build_scanline(D, H, W, x, y, c, s, r, h, smp, bilinear, hi);  // Eq. (4) + V
-                if (cand_tight) {
-                    for (const Sample& sm : smp) Tv[(size_t)sm.iy * W + sm.ix] = 1;
-                }
-                if (!cand) continue;
-                ++nc;
+                if (cand) ++nc;
                 bool round_tight = false;
-                if (Tv) {
+                if (Tv)
+                    for (const Sample& sm : smp) round_tight |= near_half(sm.px) || near_half(sm.py);
+                if (round_tight && cand) {  // (ii): the alternative pixels could be sampled
                     for (const Sample& sm : smp) {
-                        if (near_half(sm.px) || near_half(sm.py)) {
-                            round_tight = true;
-                            // the alternative pixel of the tight coordinate
-                            int ax = sm.ix, ay = sm.iy;
-                            if (near_half(sm.px)) ax = (sm.px >= (float)sm.ix) ? sm.ix + 1 : sm.ix - 1;
-                            if (near_half(sm.py)) ay = (sm.py >= (float)sm.iy) ? sm.iy + 1 : sm.iy - 1;
-                            if (ax >= 0 && ax < W && ay >= 0 && ay < H) Tv[(size_t)ay * W + ax] = 1;
-                        }
+                        int ax = sm.ix, ay = sm.iy;
+                        if (near_half(sm.px)) ax = (sm.px >= (float)sm.ix) ? sm.ix + 1 : sm.ix - 1;
+                        if (near_half(sm.py)) ay = (sm.py >= (float)sm.iy) ? sm.iy + 1 : sm.iy - 1;
+                        if ((ax != sm.ix || ay != sm.iy) && ax >= 0 && ax < W && ay >= 0 && ay < H)
+                            Fv[(size_t)ay * W + ax] = 1;
                     }
-                    if (round_tight)
-                        for (const Sample& sm : smp) Tv[(size_t)sm.iy * W + sm.ix] = 1;
                 }
                 sort_and_test(smp, zeta, beta, ns, hit);  // sort + Eq. (5)
                 const int n = (int)smp.size();
-                for (int k = 0; k < n; ++k)                // Eq. (6) (R8)
-                    if (hit[k]) Mv[(size_t)smp[k].iy * W + smp[k].ix] = 1;
+                if (cand)
+                    for (int k = 0; k < n; ++k)            // Eq. (6) (R8)
+                        if (hit[k]) Mv[(size_t)smp[k].iy * W + smp[k].ix] = 1;
                 if (!Tv) continue;
-                for (int k = 0; k < n; ++k) {
-                    // ties / near-ties of W change the sorted order
-                    if (k + 1 < n && std::fabs(smp[k + 1].W - smp[k].W) < kTightEps) {
-                        for (int j = k - ns; j <= k + 1 + ns; ++j)
-                            if (j >= 0 && j < n) Tv[(size_t)smp[j].iy * W + smp[j].ix] = 1;
-                    }
-                    // decisive comparisons close to zeta or beta
-                    for (int d = -ns; d <= ns; ++d) {
-                        if (d == 0) continue;
-                        int j = k + d;
-                        if (j < 0 || j >= n) continue;
-                        float dw = std::fabs(smp[k].W - smp[j].W);
-                        float dv = smp[j].V - smp[k].V;
-                        if ((std::fabs(zeta - dw) < kTightEps && dv > beta - kTightEps) ||
-                            (std::fabs(dv - beta) < kTightEps && dw < zeta + kTightEps))
-                            Tv[(size_t)smp[k].iy * W + smp[k].ix] = 1;
+                // which samples' hit status could flip (see the tight map rules)
+                std::vector<unsigned char> frag(n, 0);
+                if (round_tight && cand) {
+                    frag.assign(n, 1);       // any sample's V, hence any test, could change
+                } else if (cand_tight) {
+                    for (int k = 0; k < n; ++k) frag[k] = hit[k];  // hits that could (dis)appear
+                } else {
+                    for (int k = 0; k < n; ++k) frag[k] = decision_fragile(smp, k, zeta, beta, ns) ? 1 : 0;
+                    for (int k = 0; k + 1 < n; ++k) {  // (iii) near-ties: test the swapped order
+                        if (!in_margin(smp[k + 1].W - smp[k].W)) continue;
+                        std::swap(smp[k], smp[k + 1]);
+                        for (int j = std::max(0, k - ns); j <= std::min(n - 1, k + 1 + ns); ++j) {
+                            const int orig = (j == k) ? k + 1 : (j == k + 1) ? k : j;
+                            if (hit_at(smp, j, zeta, beta, ns) != (hit[orig] != 0)) frag[orig] = 1;
+                        }
+                        std::swap(smp[k], smp[k + 1]);
                     }
                 }
+                for (int k = 0; k < n; ++k) {
+                    const size_t p = (size_t)smp[k].iy * W + smp[k].ix;
+                    if (frag[k]) Fv[p] = 1;
+                    else if (hit[k] && cand) Rv[p] = 1;  // a hit no single margin can remove
+                }
             }
+        if (Tv)  // tight: some decision could flip the pixel and no robust hit holds it at 1
+            for (size_t i = 0; i < HW; ++i) Tv[i] = (Fv[i] && !Rv[i]) ? 1 : 0;
         if (n_cand) n_cand[v] = nc;
     }
     return 0;

@@ -126,3 +126,29 @@ def test_pack_angle_channels_are_cos_sin_of_atan2():
     # E = 0 (last pixel): A = atan2(0, 0) = 0
     assert x[-1, -1, 2] == 1.0 and x[-1, -1, 3] == 0.0
     np.testing.assert_array_equal(x[..., 1], C.bf16(np.hypot(ex, ey) / 8.0))
+
+
+@pytest.mark.parametrize("band", [(0.05, 0.95), (0.02, 0.98), (0.3, 0.7), (0.5, 0.5), (0.0, 1.0), (0.2, 1.0)])
+def test_tile_routing_rule(band):
+    """The routing states against their definition by probabilities: a tile
+    is filled with 0 when sigmoid(z) < lo, with 1 when sigmoid(z) > hi, else
+    it takes the exact path.  The bounds are the logits of lo and hi rounded
+    to fp32, so the rule is checked (a) against sigmoid itself wherever z is
+    more than 1e-5 from a bound, (b) exactly on the fp32 neighbours of each
+    rounded bound, (c) on infinities, signed zeros and NaN (exact path)."""
+    lo, hi = band
+    z = np.concatenate([np.linspace(-12, 12, 2001, dtype=np.float32),
+                        np.array([-np.inf, np.inf, 0.0, -0.0], np.float32)])
+    bounds = {p: np.float32(math.log(p / (1 - p))) for p in (lo, hi) if 0 < p < 1}
+    for b in bounds.values():
+        z = np.concatenate([z, [np.nextafter(b, np.float32(-np.inf)), b, np.nextafter(b, np.float32(np.inf))]])
+    st = C.tile_states(z, lo, hi)
+    for zz, s in zip(z.tolist(), st.tolist()):
+        if math.isfinite(zz) and all(abs(zz - math.log(p / (1 - p))) > 1e-5 for p in bounds):
+            sg = 1.0 / (1.0 + math.exp(-zz))
+            assert s == (0 if sg < lo else (1 if sg > hi else 2)), (zz, s)
+        zl = bounds.get(lo, -math.inf if lo <= 0 else math.inf)
+        zh = bounds.get(hi, math.inf if hi >= 1 else -math.inf)
+        assert s == (0 if zz < zl else (1 if zz > zh else 2)), (zz, s)
+    assert C.tile_states(np.array([np.nan], np.float32), lo, hi)[0] == 2
+    assert C.tile_states(np.array([-np.inf, np.inf], np.float32), 0.0, 1.0).tolist() == [2, 2]

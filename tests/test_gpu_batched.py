@@ -172,3 +172,39 @@ def test_branch_split_edge_cases(gctx, torch, ref, sizes):
     _, Ms = _run_batch(gctx, torch, frames)
     for f, M in zip(frames, Ms):
         assert np.array_equal(M.cpu().numpy(), _ref(ref, f)), f"{f.W}x{f.H}"
+
+
+def _oracle_masks(ref, frames, threads=16):
+    """The oracle on every frame, on a host thread pool (ctypes releases the
+    GIL; the oracle itself stays single-threaded per call)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(lambda f: ref.detect_scene(f, want_tight=True), frames))
+
+
+def test_c3_benched_shape(gctx, torch, ref):
+    """The batched workload exactly as the benchmark times it: 64 frames from
+    make_batch(seed 3000) (sizes 640x480 .. 2048x1536), 8 views each, launch
+    shape from the batched autotuner, the graph's branches side by side;
+    every frame and view against the oracle (bit-exact; tight map <= 0.01 %)."""
+    from paper_2408_14050_amd import occl
+    frames = scenes.make_batch(seed=3000, n_frames=64)
+    print(f"c3: {len(frames)} frames, {sum(f.pixel_views for f in frames)} pixel-views", flush=True)
+    Ds = [torch.from_numpy(f.D).cuda() for f in frames]
+    Ms = [torch.full((f.n_views, f.H, f.W), 9, dtype=torch.uint8, device="cuda") for f in frames]
+    batch = [(D, M, f.scan_len) for D, M, f in zip(Ds, Ms, frames)]
+    prm = occl.params(**frames[0].params)
+    shape = gctx.occl_autotune_batched(batch, frames[0].angles, frames[0].ratios, prm, reps=2)
+    for M in Ms:
+        M.fill_(9)
+    gctx.occl_detect_batched(batch, frames[0].angles, frames[0].ratios, prm)
+    torch.cuda.synchronize()
+    refs = _oracle_masks(ref, frames)
+    bad = 0
+    for i, (f, M, (M_ref, T, _)) in enumerate(zip(frames, Ms, refs)):
+        assert int(T.sum()) <= 1e-4 * T.size, f"frame {i}: tight map above 0.01 %"
+        diff = M.cpu().numpy() != M_ref
+        assert not (diff & (T == 0)).any(), f"frame {i} {f.W}x{f.H}: {int(diff.sum())} mismatches ({shape})"
+        bad += int(diff.sum())
+    assert bad <= 1e-4 * sum(f.pixel_views for f in frames)
+    assert {(f.W, f.H) for f in frames} == {(640, 480), (1280, 960), (1920, 1080), (2048, 1536)}

@@ -323,19 +323,8 @@ def test_cnn_calls_validate(gctx, torch):
 # routed exact fallback
 # ---------------------------------------------------------------------------
 def tile_states(z, lo, hi):
-    """0 / 1 / 2 per tile: logit below / above the bounds' logits (double,
-    rounded to fp32), else exact; NaN takes the exact path."""
-    def bound(p):
-        if p <= 0:
-            return -np.inf
-        if p >= 1:
-            return np.inf
-        return np.float32(math.log(p / (1.0 - p)))
-    zl, zh = bound(lo), bound(hi)
-    s = np.full(z.shape, 2, np.uint8)
-    s[z < zl] = 0
-    s[z > zh] = 1
-    return s
+    """The oracle's routing rule (probability band -> fill 0 / fill 1 / exact)."""
+    return cnn_ref.tile_states(z, lo, hi)
 
 
 def expand(st, H, W):

@@ -1,10 +1,11 @@
 """GPU parity of the exact path: the HIP library (through its C ABI) against
 the CPU oracle, element by element, on seeded synthetic scenes.
 
-Bar: bit-exact masks.  The oracle's `tight` map (pixels within 1e-4 px of a
-decision threshold) would exempt mismatches, capped at 0.01 % of the
-pixels; every test here additionally reports the mismatch count, which has
-been zero throughout.
+Bar: bit-exact masks.  The oracle's `tight` map (pixels whose value rests on
+a decision within 1e-4 px of its threshold, at most 0.01 % of the pixels,
+checked here on every map passed in) would exempt mismatches; every test
+here additionally reports the mismatch count, which has been zero
+throughout.
 """
 import numpy as np
 import pytest
@@ -43,6 +44,8 @@ def run_gpu(gctx, torch, D, angles, ratios, L, counts=False, **kw):
 def assert_parity(M_gpu, M_ref, tight=None, what=""):
     diff = M_gpu != M_ref
     n_bad = int(diff.sum())
+    if tight is not None:
+        assert int(tight.sum()) <= 1e-4 * M_ref.size, f"{what}: tight map above 0.01 %"
     if n_bad and tight is not None:
         assert not (diff & (tight == 0)).any(), f"{what}: {n_bad} mismatches outside the tight map"
         assert n_bad <= 1e-4 * M_ref.size, f"{what}: {n_bad} mismatches > 0.01 %"
@@ -87,20 +90,15 @@ def test_c2_crops_parity(gctx, torch, ref, seed):
         assert_parity(M, M_ref, T, f"c2 crop {seed} ({y0},{x0})")
 
 
-def test_c2_full_frame_sampled(gctx, torch, ref):
-    """Full 3840x2160 x 15 views on the GPU; the oracle recomputes sampled
-    windows (every candidate that can reach a window, processed exactly as
-    in the full detector)."""
+def test_c2_full_frame(gctx, torch, ref):
+    """Full 3840x2160 x 15 views (L up to 366) against the whole-frame oracle."""
     sc = scenes.make_scene("c2", 2000)
+    print(f"c2 seed 2000 {sc.W}x{sc.H} x{sc.n_views} views", flush=True)
+    M_ref, T, nc_ref = ref.detect_scene(sc, want_tight=True)
     M, nc = run_gpu(gctx, torch, sc.D, sc.angles, sc.ratios, sc.scan_len, counts=True, **sc.params)
-    rng = np.random.default_rng(7)
-    wins = [(0, 0), (sc.W - 96, sc.H - 96), (0, sc.H - 96), (sc.W - 96, 0)]
-    wins += [(int(rng.integers(0, sc.W - 96)), int(rng.integers(0, sc.H - 96))) for _ in range(8)]
-    for x0, y0 in wins:
-        Mw = ref.detect_window(sc.D, sc.angles, sc.ratios, sc.scan_len, x0, y0, x0 + 96, y0 + 96,
-                               **sc.params)
-        assert_parity(M[:, y0:y0 + 96, x0:x0 + 96], Mw, None, f"c2 window ({x0},{y0})")
-    assert (nc > 0).all()
+    np.testing.assert_array_equal(nc, nc_ref)
+    assert_parity(M, M_ref, T, "c2 full frame")
+    assert M_ref.sum() > 0
 
 
 def test_c4_frame_parity(gctx, torch, ref):

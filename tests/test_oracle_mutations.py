@@ -60,18 +60,43 @@ MUTANTS = {
     # median fusion
     "median_even_takes_lower": ("(v[m / 2 - 1] + v[m / 2]) * 0.5f", "v[m / 2 - 1]"),
     "median_keeps_nan": ("if (!std::isnan(x)) v.push_back(x);", "v.push_back(x);"),
+    # the tight map (parity exemption)
+    "tight_structural_zero_dot": ("if (dot == 0.0f) return a != 0.0f && b != 0.0f;",
+                                  "if (dot == 0.0f) return true;"),
+    "tight_cancellation_ignored": ("if (dot == 0.0f) return a != 0.0f && b != 0.0f;",
+                                   "if (dot == 0.0f) return false;"),
+    "tight_edge_margin": ("const bool cand_tight = Tv && E[i] > gamma && dot_margin_tight(ex[i], ey[i], c, s);",
+                          "const bool cand_tight = Tv && ((E[i] > gamma && dot_margin_tight(ex[i], ey[i], c, s)) "
+                          "|| std::fabs(E[i] - gamma) < kTightEps);"),
+    "tight_exact_zero_margin": ("inline bool in_margin(float m) { return m != 0.0f && std::fabs(m) < kTightEps; }",
+                                "inline bool in_margin(float m) { return std::fabs(m) < kTightEps; }"),
+    "tight_swap_skipped": ("if (!in_margin(smp[k + 1].W - smp[k].W)) continue;", "continue;"),
+    "tight_robust_cover_ignored": ("Tv[i] = (Fv[i] && !Rv[i]) ? 1 : 0;", "Tv[i] = Fv[i] ? 1 : 0;"),
+    "tight_rounding_ignored": ("round_tight |= near_half(sm.px) || near_half(sm.py);", "round_tight |= false;"),
+    "tight_zeta_margin_ignored": ("const bool m = (in_margin(zeta - dw) && dv > beta - kTightEps) ||",
+                                  "const bool m = false ||"),
+    "tight_beta_margin_ignored": ("                       (in_margin(dv - beta) && dw < zeta + kTightEps);\n        if (m) near = true;",
+                                  "                       false;\n        if (m) near = true;"),
+    # the windowed checker of full-size frames
+    "window_reach_short": ("const int ya = std::max(0, y0 - h - 1), yb = std::min(H, y1 + h + 1);",
+                           "const int ya = std::max(0, y0 - h / 2), yb = std::min(H, y1 + h / 2);"),
+    # tile routing of the learned proposal (oracle/cnn_ref.py)
+    "routing_lower_bound_non_strict": ("cnn_ref.py", "s[z < zl] = 0", "s[z <= zl] = 0"),
+    "routing_upper_bound_non_strict": ("cnn_ref.py", "s[z > zh] = 1", "s[z >= zh] = 1"),
+    "routing_nan_filled": ("cnn_ref.py", "s[z < zl] = 0", "s[~(z >= zl)] = 0"),
+    "routing_bound_not_logit": ("cnn_ref.py", "return np.float32(np.log(p / (1.0 - p)))", "return np.float32(p)"),
 }
 
 # every CPU pin file that exercises the oracle
 PIN_FILES = ("test_oracle_pins.py", "test_bilinear.py", "test_quality_oracle.py", "test_fusion.py",
-             "test_thin_oracle.py")
+             "test_thin_oracle.py", "test_tight_pins.py", "test_cnn_oracle.py")
 
 
 @pytest.mark.slow
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_pins_catch_mutant(name, tmp_path):
-    old, new = MUTANTS[name]
-    src = open(os.path.join(ROOT, "oracle", "occl_ref.cpp")).read()
+    fname, old, new = MUTANTS[name] if len(MUTANTS[name]) == 3 else ("occl_ref.cpp",) + MUTANTS[name]
+    src = open(os.path.join(ROOT, "oracle", fname)).read()
     assert src.count(old) >= 1, f"mutation site for {name} not found"
     ign = shutil.ignore_patterns("*.so", "__pycache__", "*.tmp")
     shutil.copytree(os.path.join(ROOT, "oracle"), tmp_path / "oracle", ignore=ign)
@@ -81,8 +106,9 @@ def test_pins_catch_mutant(name, tmp_path):
     for f in ("conftest.py",) + PIN_FILES:
         shutil.copy(os.path.join(ROOT, "tests", f), tmp_path / "tests" / f)
     shutil.copytree(os.path.join(ROOT, "tests", "golden"), tmp_path / "tests" / "golden")
-    (tmp_path / "oracle" / "occl_ref.cpp").write_text(src.replace(old, new))
-    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider", "-m", "not gpu"]
+    (tmp_path / "oracle" / fname).write_text(src.replace(old, new))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider", "-m",
+                        "not gpu and not slow"]
                        + [f"tests/{f}" for f in PIN_FILES], cwd=tmp_path, capture_output=True, text=True,
                        timeout=300)
     assert r.returncode != 0, f"mutant {name} survived every pin:\n{r.stdout[-2000:]}"
