@@ -1,16 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the exact occlusion detector on one MI355X.
 
-Workload (one "step"): one 1280x960 fp32 fused disparity map of a 3x3
-camera array with its 8 peripheral views (axis views r = 1, diagonal views
-r = sqrt(2)), 20 objects with disparity in [0, 48], noise 0.1 px,
-L_v = ceil(max(D) * r_v) + 2, gamma = 1, beta = 0.5, zeta = 1, N = 1:
-edges + candidates (Eqs. 1-2), scanlines, warp, sort, occlusion test and
-mask (Eqs. 4-6) for all 8 views.  D and M stay resident in HBM.
+Headline workload (one "step"): one batched launch of 64 fp32 disparity maps
+of mixed size (640x480, 1280x960, 1920x1080, 2048x1536; seed 3000), each
+with the 8 peripheral views of a 3x3 camera array (axis views r = 1,
+diagonal views r = sqrt(2)), c1 scene statistics (objects with disparity in
+[0, 48], noise 0.1 px), per-frame L_v = ceil(max(D) * r_v) + 2, gamma = 1,
+beta = 0.5, zeta = 1, N = 1: edges + candidates (Eqs. 1-2), scanlines, warp,
+sort, occlusion test and mask (Eqs. 4-6) of every frame and view in one
+graph launch.  D and M stay resident in HBM.
 
-Prints ONE JSON line.  `value` is Mpixel-views/s of the whole step;
-`roofline` describes the dominant kernel, timed with HIP events on the
-library's stream; `cpu_baseline` is the CPU oracle on the host cores.
+Prints ONE JSON line.  `value` is Mpixel-views/s of the whole batch;
+`roofline` describes the dominant kernel (the batched scanline pass) timed
+with HIP events on the library's stream; `cpu_baseline` is the CPU oracle on
+the host cores over (frame, view) jobs of the same workload.  Secondary
+sections: single 1280x960 frames with frames in flight (c1), one 3840x2160
+frame with 15 views (c2), 1920x1080 frames (c4, exact and learned), quality,
+fusion, thinning and the paper's Table 3 shape as context.
 """
 from __future__ import annotations
 
@@ -89,69 +95,119 @@ def traffic_for(kernel: str, workload: str):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    e = t.get(kernel, {})
+    e = t.get(traffic_key(kernel, workload), {})
     if e.get("kernel_hash") != kernel_hash(kernel) or e.get("workload") != workload:
         return None
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(sc, seconds: float):
-    """The CPU oracle, unchanged and single-threaded per call, run over
-    independent views of the same frame on a thread pool of the host's cores
-    (ctypes releases the GIL), for a bounded time."""
+def traffic_key(kernel: str, workload: str) -> str:
+    """Entry of profiles/traffic.json: one per kernel and workload."""
+    return f"{kernel} @ {workload}"
+
+
+def host_cpu():
+    """nproc, the threads this process may use (the job's share of the host)
+    and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    return {"nproc": os.cpu_count(), "usable": usable, "model": model}
+
+
+def cpu_baseline(frames, seconds: float, max_threads: int = 16):
+    """The CPU oracle, unchanged and single-threaded per call, on the
+    headline workload for a bounded time:
+      all cores: independent (frame, view) jobs of the batch, dealt to a
+        thread pool (ctypes releases the GIL) of the host's usable threads,
+        capped at the job's share of 16;
+      one core: whole frames, all views in one oracle call (Eq. (1) once per
+        frame).
+    Throughput is the pixel-views of the completed jobs over the elapsed
+    time."""
     from concurrent.futures import ThreadPoolExecutor
     from oracle import occl_ref
 
-    p = sc.params
-    jobs = [(sc.angles[v:v + 1], sc.ratios[v:v + 1], sc.scan_len[v:v + 1]) for v in range(sc.n_views)]
+    cpu = host_cpu()
+    threads = max(1, min(max_threads, cpu["usable"]))
+    jobs = [(f, v) for f in frames for v in range(f.n_views)]
 
-    def one(j):
-        occl_ref.detect(sc.D, j[0], j[1], j[2], p["edge_thr"], p["disp_thr"], p["dist_thr"],
-                        p["neighbours"])
+    def one(job):
+        f, v = job
+        p = f.params
+        occl_ref.detect(f.D, f.angles[v:v + 1], f.ratios[v:v + 1], f.scan_len[v:v + 1], p["edge_thr"],
+                        p["disp_thr"], p["dist_thr"], p["neighbours"])
+        return f.H * f.W
 
-    # single thread: whole frames
     t0 = time.perf_counter()
-    frames1 = 0
-    while True:
-        for j in jobs:
-            one(j)
-        frames1 += 1
-        if time.perf_counter() - t0 > seconds / 3:
-            break
+    pv1, n1 = 0, 0
+    while time.perf_counter() - t0 < seconds / 3:
+        f = frames[n1 % len(frames)]
+        p = f.params
+        occl_ref.detect(f.D, f.angles, f.ratios, f.scan_len, p["edge_thr"], p["disp_thr"],
+                        p["dist_thr"], p["neighbours"])
+        pv1 += f.pixel_views
+        n1 += 1
     t1 = time.perf_counter() - t0
-    threads = max(1, min(16, os.cpu_count() or 1))
     t0 = time.perf_counter()
-    framesn = 0
+    pvn, nj = 0, 0
     with ThreadPoolExecutor(threads) as ex:
-        while True:
-            list(ex.map(one, jobs))
-            framesn += 1
-            if time.perf_counter() - t0 > 2 * seconds / 3:
-                break
+        while time.perf_counter() - t0 < 2 * seconds / 3:
+            chunk = [jobs[(nj + i) % len(jobs)] for i in range(4 * threads)]
+            pvn += sum(ex.map(one, chunk))
+            nj += len(chunk)
     tn = time.perf_counter() - t0
-    pv = sc.pixel_views
     return {
-        "value": round(pv * framesn / tn / 1e6, 3), "unit": "Mpixel-views/s", "cores": threads,
+        "value": round(pvn / tn / 1e6, 3), "unit": "Mpixel-views/s", "cores": threads,
         "kind": "oracle",
-        "sample": f"{framesn} full frames of the step's workload (8 views each, one view per job) "
-                  f"on {threads} threads in {tn:.1f} s",
-        "single_thread": {"value": round(pv * frames1 / t1 / 1e6, 3), "cores": 1,
-                          "sample": f"{frames1} full frames in {t1:.1f} s"},
+        "sample": f"{nj} (frame, view) jobs of the 64-frame batch (seed 3000), one view per oracle "
+                  f"call, on {threads} threads in {tn:.1f} s",
+        "host": cpu,
+        "single_thread": {"value": round(pv1 / t1 / 1e6, 3), "cores": 1,
+                          "sample": f"{n1} whole frames of the batch (all 8 views per call) in {t1:.1f} s"},
     }
+
+
+def bitonic_ops(n_cand, scan_len, neighbours=1):
+    """Algorithmic ALU work of Eqs. (4)-(6) as the survey counts it: per
+    scanline of n samples a bitonic sort of n' = 2^ceil(log2 n) keys,
+    (n'/2) log2 n' (log2 n' + 1) / 2 compare-exchanges, plus 2 n_s n
+    neighbour tests."""
+    ns = max(1, (neighbours + 1) // 2)
+    tot = 0
+    for c, L in zip(n_cand, scan_len):
+        n = 2 * (int(L) // 2) + 1
+        lg = max(1, math.ceil(math.log2(n)))
+        tot += int(c) * ((1 << lg) // 2 * lg * (lg + 1) // 2 + 2 * ns * n)
+    return tot
 
 
 # ---------------------------------------------------------------------------
 # profiling helpers (run under rocprofv3 on the GPU, summarised here)
 # ---------------------------------------------------------------------------
 PROFILE_CMD = ("rocprofv3 {mode} -d gpurun_out/{out} -o run -- python3 bench.py --steps 20 "
-               "--warmup 2 --prewarm 0 --streams 1 --no-cpu-baseline --no-context --no-check "
-               "--no-learned --no-quality")
+               "--warmup 2 --prewarm-batched 0 --prewarm 0 --c1-steps 20 --streams 1 --no-c2 "
+               "--no-cpu-baseline --no-context --no-check --no-learned --no-quality")
 QUALITY_PROFILE_CMD = ("rocprofv3 {mode} -d gpurun_out/{out} -o run -- python3 bench.py "
                        "--quality-only")
 THIN_PROFILE_CMD = "rocprofv3 {mode} -d gpurun_out/{out} -o run -- python3 bench.py --thin-only"
 LEARNED_PROFILE_CMD = ("rocprofv3 {mode} -d gpurun_out/{out} -o run -- python3 bench.py --learned-only "
                        "--learned-steps 10 --learned-eval 1")
 BATCH_WORKLOAD = "c3 64 mixed frames seed 3000"
+C1_WORKLOAD = "c1 1280x960 x8 views seed 1002"
+C2_WORKLOAD = "c2 3840x2160 x15 views seed 2000"
+C2_PROFILE_CMD = "rocprofv3 {mode} -d gpurun_out/{out} -o run -- python3 bench.py --c2-only --c2-steps 5"
+C2_KERNELS = ("k_edges<0>", "k_scanlines<4, 0>", "k_scanlines<8, 0>")
 QUALITY_WORKLOAD = "c1 1280x960 x8 views seeds 1000-1003"
 LEARNED_WORKLOAD = "c4 1920x1080 x8 views seed 4100"
 THIN_WORKLOAD = "c1 1280x960 x8 views seed 1002 thinned"
@@ -231,7 +287,8 @@ def profiles_from(run_dir: str, workload: str) -> int:
     runs = [("", PROFILE_CMD, lambda k: not k.startswith(LEARNED_KERNELS + QUALITY_KERNELS)),
             ("l", LEARNED_PROFILE_CMD, lambda k: k.startswith(LEARNED_KERNELS)),
             ("q", QUALITY_PROFILE_CMD, lambda k: k.startswith(QUALITY_KERNELS)),
-            ("t", THIN_PROFILE_CMD, lambda k: k.startswith(THIN_KERNELS))]
+            ("t", THIN_PROFILE_CMD, lambda k: k.startswith(THIN_KERNELS)),
+            ("c", C2_PROFILE_CMD, lambda k: k.startswith(C2_KERNELS))]
     for pre, cmd, keep in runs:
         if not db(pre + "prof"):
             continue
@@ -245,12 +302,14 @@ def profiles_from(run_dir: str, workload: str) -> int:
                 wl = QUALITY_WORKLOAD
             elif pre == "t":
                 wl = THIN_WORKLOAD
+            elif pre == "c":
+                wl = C2_WORKLOAD
             else:
-                wl = BATCH_WORKLOAD if "batched" in k else workload
+                wl = BATCH_WORKLOAD if ("batched" in k or "finish_frames" in k) else workload
             tag = wl.split(":")[0].replace(" ", "_").replace("x8_views", "v8")
             rd = fetch[k] * 1024 / (f_read or 1.0)
             wr = write[k] * 1024 / (f_write or 1.0)
-            traffic[k] = {"kernel_hash": kernel_hash(k), "source": kernel_source(k), "workload": wl,
+            traffic[traffic_key(k, wl)] = {"kernel_hash": kernel_hash(k), "source": kernel_source(k), "workload": wl,
                           "fetch_kib": fetch[k], "write_kib": write[k], "bytes_per_launch": round(rd + wr),
                           "read_bytes": round(rd), "write_bytes": round(wr),
                           "avg_us": round(trace[k]["avg_us"], 3)}
@@ -327,9 +386,10 @@ def tune_in_flight(ctxs, run, reps: int = 200):
     return {"edge_rows": best[1], "scan_blocks_per_cu": best[2]}
 
 
-def bench_batched(ctx, steps: int, tune: bool):
-    """64 frames of mixed size (640x480 .. 2048x1536, c1 statistics, 8 views,
-    per-frame L) in one graph launch per step."""
+def bench_c3(ctx, args):
+    """The headline: 64 frames of mixed size (640x480 .. 2048x1536, c1
+    statistics, 8 views, per-frame L) in one graph launch per step."""
+    import numpy as np
     import torch
     from paper_2408_14050_amd import occl, scenes
     frames = scenes.make_batch(seed=3000, n_frames=64)
@@ -337,23 +397,187 @@ def bench_batched(ctx, steps: int, tune: bool):
     Ms = [torch.empty((f.n_views, f.H, f.W), dtype=torch.uint8, device="cuda") for f in frames]
     batch = [(D, M, f.scan_len) for D, M, f in zip(Ds, Ms, frames)]
     prm = occl.params(**frames[0].params)
+    angles, ratios = frames[0].angles, frames[0].ratios
     shape = None
-    if tune:
-        shape = ctx.occl_autotune_batched(batch, frames[0].angles, frames[0].ratios, prm, reps=3)
-    for _ in range(3):
-        ctx.occl_detect_batched(batch, frames[0].angles, frames[0].ratios, prm)
+    if not args.no_tune:  # launch shape chosen by the autotuner (not timed)
+        shape = ctx.occl_autotune_batched(batch, angles, ratios, prm, reps=3)
+    # untimed pre-warm (the HIP runtime's one-off stall some thousand
+    # launches into a process stays out of the timed region)
+    for _ in range(max(args.warmup, args.prewarm_batched)):
+        ctx.occl_detect_batched(batch, angles, ratios, prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.occl_detect_batched(batch, angles, ratios, prm)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    dt = elapsed / args.steps
+    pv = sum(f.pixel_views for f in frames)
+    alg = sum((4 + f.n_views) * f.H * f.W for f in frames)
+    # the dominant kernel alone: the batch's stages re-run outside the graph
+    # between HIP events on the context's stream
+    stages = ctx.occl_time_batched(max(3, min(args.steps, 20)))
+    out = {"value": pv * args.steps / elapsed / 1e6, "ms_per_step": dt * 1e3, "pixel_views": pv,
+           "alg_bytes": alg, "frames": frames, "masks": Ms, "launch_shape": shape, "stages_ms": stages}
+    scan_ms = stages["scanlines"]
+    roof = {"kernel": "k_scanlines_batched<2, 0>", "bound": "hbm",
+            "achieved": round(alg / (scan_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(alg / (scan_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+            "traffic": None, "avg_ms": round(scan_ms, 5), "launches_per_step": ctx_branches(),
+            "bytes_per_step": alg,
+            "note": "algorithmic bytes of the batch (D read once, every mask byte written once) over "
+                    "the batched scanline pass's time per batch (its launches re-run outside the "
+                    "graph, branch after branch, between HIP events)"}
+    t = traffic_for("k_scanlines_batched<2, 0>", BATCH_WORKLOAD)
+    if t is not None:
+        roof["traffic"] = t * roof["launches_per_step"]
+    out["roofline"] = roof
+    if not args.no_check:
+        from concurrent.futures import ThreadPoolExecutor
+        from oracle import occl_ref
+        with ThreadPoolExecutor(max(1, min(16, host_cpu()["usable"]))) as ex:
+            refs = list(ex.map(lambda f: occl_ref.detect_scene(f), frames))
+        bad = 0
+        n_cand = []
+        for (M_ref, _, nc), M in zip(refs, Ms):
+            bad += int((M.cpu().numpy() != M_ref).sum())
+            n_cand.append(nc)
+        out["parity"] = {"frames": len(frames), "mismatches": bad}
+        ops = sum(bitonic_ops(nc, f.scan_len) for nc, f in zip(n_cand, frames))
+        out["alu"] = {"kernel": "k_scanlines_batched<2, 0>", "ops_per_step": ops,
+                      "count": "bitonic compare-exchanges of 2^ceil(log2 n) keys + 2 n neighbour tests "
+                               "per scanline",
+                      "achieved_gops": round(ops / (scan_ms * 1e-3) / 1e9, 1), "peak_gops": ALU_PEAK_GOPS,
+                      "frac": round(ops / (scan_ms * 1e-3) / 1e9 / ALU_PEAK_GOPS, 4),
+                      "scanlines": int(sum(int(np.sum(nc)) for nc in n_cand))}
+    return out
+
+
+def ctx_branches():
+    """Graph branches of a batched launch (the library's default split)."""
+    return 2
+
+
+def bench_c1(args):
+    """Single 1280x960 frames (c1, seed args.seed) one at a time and with
+    frames in flight on separate streams."""
+    import numpy as np
+    import torch
+    from paper_2408_14050_amd import occl, scenes
+    sc = scenes.make_scene("c1", args.seed)
+    H, W, V = sc.H, sc.W, sc.n_views
+    D = torch.from_numpy(sc.D).cuda()
+    M = torch.empty((V, H, W), dtype=torch.uint8, device="cuda")
+    ctx = occl.Context(0, max_pixels_hint=H * W, max_views_hint=V)
+    prm = occl.params(**sc.params, scan_len_per_view=sc.scan_len)
+    steps = args.c1_steps
+    tune = None
+    if not args.no_tune:
+        tune = ctx.occl_autotune(D, sc.angles, sc.ratios, prm, M, reps=20)
+    det = ctx.occl_detect_prepared(sc.angles, sc.ratios, prm)
+    for _ in range(args.prewarm):
+        det(D, M)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        ctx.occl_detect_batched(batch, frames[0].angles, frames[0].ratios, prm)
+        det(D, M)
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
-    pv = sum(f.pixel_views for f in frames)
-    alg = sum((4 + f.n_views) * f.H * f.W for f in frames)
-    return {"workload": "c3: 64 frames from {640x480, 1280x960, 1920x1080, 2048x1536}, 8 views, "
-                        "seed 3000", "frames_per_s": round(64 / dt, 1),
-            "ms_per_launch": round(dt * 1e3, 4), "mpixel_views_per_s": round(pv / dt / 1e6, 1),
-            "alg_gbps": round(alg / dt / 1e9, 1), "launch_shape": shape}
+    single_ms = (time.perf_counter() - t0) * 1e3 / steps
+    # frames in flight: one context (workspace) and one output per HIP stream
+    S = max(1, args.streams)
+    fl_streams = [torch.cuda.Stream() for _ in range(S)]
+    fl_ctxs = [occl.Context(0, stream=st, max_pixels_hint=H * W, max_views_hint=V) for st in fl_streams]
+    fl_Ms = [torch.empty((V, H, W), dtype=torch.uint8, device="cuda") for _ in range(S)]
+    fl_Ds = [D.clone() for _ in range(S)]
+    torch.cuda.synchronize()
+    if not args.no_tune:
+        for c, m in zip(fl_ctxs, fl_Ms):
+            c.occl_autotune(D, sc.angles, sc.ratios, prm, m, reps=20)
+    fl_det = [c.occl_detect_prepared(sc.angles, sc.ratios, prm) for c in fl_ctxs]
+
+    def run(n):
+        for i in range(n):
+            k = i % S
+            fl_det[k](fl_Ds[k], fl_Ms[k])
+
+    fl_shape = None
+    if not args.no_tune and S > 1:
+        fl_shape = tune_in_flight(fl_ctxs, run)
+    run(args.prewarm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    fl_bad = sum(int((m != M).sum().item()) for m in fl_Ms)
+    for c in fl_ctxs:
+        c.occl_release()
+    ctx.occl_profile_enable(True)
+    for _ in range(min(steps, 200)):
+        ctx.occl_detect(D, sc.angles, sc.ratios, prm, M=M)
+    prof = ctx.occl_profile_read()
+    ctx.occl_profile_enable(False)
+    n_cand = ctx.occl_last_candidate_counts(V)
+    scan_rep = ctx.occl_time_scanlines(200)
+    alg = (4 + V) * H * W
+    ms_fl = elapsed * 1e3 / steps
+    out = {"workload": C1_WORKLOAD, "frames_in_flight": S, "in_flight_launch_shape": fl_shape,
+           "ms_per_frame": round(ms_fl, 5), "value": round(H * W * V / (ms_fl * 1e-3) / 1e6, 1),
+           "hbm_frac": round(alg / (ms_fl * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+           "single_stream": {"ms_per_frame": round(single_ms, 5),
+                             "value": round(H * W * V / (single_ms * 1e-3) / 1e6, 1)},
+           "stages_ms": {k: round(prof[k][0] / max(1, prof[k][1]), 5) for k in ("edges", "scanlines")},
+           "scanline_pass_ms": round(scan_rep, 5), "launch_shape": tune,
+           "scanline_hbm_frac": round(alg / (scan_rep * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+           "scanline_alu_frac": round(bitonic_ops(n_cand, sc.scan_len) / (scan_rep * 1e-3) / 1e9
+                                      / ALU_PEAK_GOPS, 4),
+           "candidates_per_view": [int(x) for x in n_cand]}
+    if not args.no_check:
+        from oracle import occl_ref
+        M_ref, _, nc_ref = occl_ref.detect_scene(sc)
+        out["parity"] = {"mismatches": int((M.cpu().numpy() != M_ref).sum()),
+                         "candidates_equal": bool(np.array_equal(n_cand, nc_ref)),
+                         "frames_in_flight_disagreeing_bytes": fl_bad}
+    ctx.occl_release()
+    return out
+
+
+def bench_c2(ctx, steps: int, tune: bool = True):
+    """One 3840x2160 frame with 15 views of a 4x4 array (L up to 366)."""
+    import torch
+    from paper_2408_14050_amd import occl, scenes
+    sc = scenes.make_scene("c2", 2000)
+    H, W, V = sc.H, sc.W, sc.n_views
+    D = torch.from_numpy(sc.D).cuda()
+    M = torch.empty((V, H, W), dtype=torch.uint8, device="cuda")
+    prm = occl.params(**sc.params, scan_len_per_view=sc.scan_len)
+    shape = ctx.occl_autotune(D, sc.angles, sc.ratios, prm, M, reps=3) if tune else None
+    for _ in range(3):
+        ctx.occl_detect(D, sc.angles, sc.ratios, prm, M=M)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.occl_detect(D, sc.angles, sc.ratios, prm, M=M)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    ctx.occl_profile_enable(True)
+    for _ in range(steps):
+        ctx.occl_detect(D, sc.angles, sc.ratios, prm, M=M)
+    prof = ctx.occl_profile_read()
+    ctx.occl_profile_enable(False)
+    n_cand = ctx.occl_last_candidate_counts(V)
+    scan_rep = ctx.occl_time_scanlines(steps)
+    alg = (4 + V) * H * W
+    ops = bitonic_ops(n_cand, sc.scan_len)
+    return {"workload": C2_WORKLOAD, "ms": round(ms, 4), "value": round(H * W * V / (ms * 1e-3) / 1e6, 1),
+            "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+            "stages_ms": {k: round(prof[k][0] / max(1, prof[k][1]), 4) for k in ("edges", "scanlines")},
+            "scanline_pass_ms": round(scan_rep, 4), "scan_kernels": scan_kernels(sc.scan_len),
+            "alu": {"ops": ops, "achieved_gops": round(ops / (scan_rep * 1e-3) / 1e9, 1),
+                    "peak_gops": ALU_PEAK_GOPS,
+                    "frac": round(ops / (scan_rep * 1e-3) / 1e9 / ALU_PEAK_GOPS, 4)},
+            "scan_len": [int(x) for x in sc.scan_len], "candidates": int(sum(n_cand)),
+            "launch_shape": shape}
 
 
 def bench_quality(ctx, n_frames: int = 4):
@@ -387,6 +611,22 @@ def bench_quality(ctx, n_frames: int = 4):
         out[name] = {"precision": round(P, 4), "recall": round(R, 4), "f1": round(2 * P * R / (P + R), 4),
                      "f1_per_frame_mean": round(sum(per_frame) / len(per_frame), 4),
                      "iou": round(tp / max(1, tp + fp + fn), 4)}
+    # the limitation cases of Sec. 5: what the method (on the GPU) misses
+    # against a ground truth of every painted surface
+    from oracle import layered_gt
+    lim = {}
+    for kind in scenes.LIMITATION_CASES:
+        sl, layers = scenes.limitation_scene(kind)
+        Dl = torch.from_numpy(sl.D).cuda()
+        Ml = ctx.occl_detect(Dl, sl.angles, sl.ratios,
+                             occl.params(**sl.params, scan_len_per_view=sl.scan_len)).cpu().numpy()
+        Zt = layered_gt.zbuffer_layers(sl.D, layers, sl.angles, sl.ratios, sl.params["disp_thr"])
+        tp = int((Ml.astype(bool) & Zt.astype(bool)).sum())
+        lim[kind] = {"true_occluded": int(Zt.sum()), "found": tp,
+                     "missed": int((Zt.astype(bool) & ~Ml.astype(bool)).sum()),
+                     "false": int((Ml.astype(bool) & ~Zt.astype(bool)).sum()),
+                     "recall": round(tp / max(1, int(Zt.sum())), 4)}
+    out["limitations_sec5"] = lim
     sc = scenes.make_scene("c1", 1000)
     D = torch.from_numpy(sc.D).cuda()
     Z = ctx.occl_zbuffer(D, sc.angles, sc.ratios, 0.5)
@@ -533,17 +773,22 @@ def bench_learned(ctx, steps: int, n_eval: int):
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=200, help="timed batched launches (headline)")
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--seed", type=int, default=1002)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--prewarm-batched", type=int, default=300,
+                    help="untimed batched launches before the timed region")
+    ap.add_argument("--seed", type=int, default=1002, help="c1 frame of the single-frame section")
+    ap.add_argument("--c1-steps", type=int, default=1000)
+    ap.add_argument("--c2-steps", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-context", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--batched-steps", type=int, default=20)
+    ap.add_argument("--no-c1", action="store_true")
+    ap.add_argument("--no-c2", action="store_true")
+    ap.add_argument("--c2-only", action="store_true", help="only the 3840x2160 x15 section")
     ap.add_argument("--profiles-from", default=None, metavar="DIR")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-only", action="store_true", help="only the learned-path section")
@@ -551,23 +796,22 @@ def main() -> int:
     ap.add_argument("--quality-only", action="store_true", help="only the quality and fusion sections")
     ap.add_argument("--thin-only", action="store_true", help="only the candidate-thinning section")
     ap.add_argument("--streams", type=int, default=3,
-                    help="frames in flight: contexts on separate HIP streams, steps round-robin")
+                    help="c1 section: frames in flight on separate HIP streams")
     ap.add_argument("--prewarm", type=int, default=PREWARM_STEPS,
-                    help="untimed steps before each timed region of the headline workload")
+                    help="c1 section: untimed steps before each timed region")
     ap.add_argument("--learned-steps", type=int, default=50)
     ap.add_argument("--learned-eval", type=int, default=4, help="c4 frames for IoU / P / R")
     args = ap.parse_args()
     if args.copy_probe:
         return copy_probe(args.copy_probe)
     if args.profiles_from:
-        return profiles_from(args.profiles_from, f"c1 1280x960 x8 views seed {args.seed}")
+        return profiles_from(args.profiles_from, C1_WORKLOAD)
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the detector's "
               "sharding across GPUs is not built", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
     from paper_2408_14050_amd import occl, scenes
 
@@ -590,130 +834,44 @@ def main() -> int:
                           "thinning": bench_thin(ctx, args.seed)}), flush=True)
         ctx.occl_release()
         return 0
-    sc = scenes.make_scene("c1", args.seed)
-    H, W, V = sc.H, sc.W, sc.n_views
-    D = torch.from_numpy(sc.D).cuda()
-    M = torch.empty((V, H, W), dtype=torch.uint8, device="cuda")
-    ctx = occl.Context(0, max_pixels_hint=H * W, max_views_hint=V)
-    prm = occl.params(**sc.params, scan_len_per_view=sc.scan_len)
+    if args.c2_only:
+        ctx = occl.Context(0)
+        print(json.dumps({"c2": bench_c2(ctx, args.c2_steps, not args.no_tune)}), flush=True)
+        ctx.occl_release()
+        return 0
 
-    tune = None
-    if not args.no_tune:  # launch shape chosen by the autotuner (not timed)
-        tune = ctx.occl_autotune(D, sc.angles, sc.ratios, prm, M, reps=20)
-
-    # Untimed pre-warm: the HIP runtime grows its dispatch resources once,
-    # some thousand launches into a process, with a stall of tens of ms; it
-    # must not land inside a timed region.
-    det = ctx.occl_detect_prepared(sc.angles, sc.ratios, prm)
-    for _ in range(max(args.warmup, args.prewarm)):
-        det(D, M)
-    torch.cuda.synchronize()
-    # one frame at a time on the context's stream: per-frame latency
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        det(D, M)
-    torch.cuda.synchronize()
-    single_ms = (time.perf_counter() - t0) * 1e3 / args.steps
-
-    # frames in flight: one context (workspace) and one output per HIP stream
-    # (non-blocking streams from torch's pool), steps dealt round-robin, so one
-    # frame's latency-bound edge pass overlaps another's issue-bound scanline
-    # pass; this is the step throughput reported as `value`
-    S = max(1, args.streams)
-    fl_streams = [torch.cuda.Stream() for _ in range(S)]
-    fl_ctxs = [occl.Context(0, stream=st, max_pixels_hint=H * W, max_views_hint=V) for st in fl_streams]
-    fl_Ms = [torch.empty((V, H, W), dtype=torch.uint8, device="cuda") for _ in range(S)]
-    fl_Ds = [D.clone() for _ in range(S)]  # each stream reads its own copy of the frame
-    torch.cuda.synchronize()
-    if not args.no_tune:
-        for c, m in zip(fl_ctxs, fl_Ms):
-            c.occl_autotune(D, sc.angles, sc.ratios, prm, m, reps=20)  # same shape: same choice
-
-    fl_det = [c.occl_detect_prepared(sc.angles, sc.ratios, prm) for c in fl_ctxs]
-
-    def run(n):
-        for i in range(n):
-            k = i % S
-            fl_det[k](fl_Ds[k], fl_Ms[k])
-
-    fl_shape = None
-    if not args.no_tune and S > 1:
-        fl_shape = tune_in_flight(fl_ctxs, run)
-    run(max(args.warmup, args.prewarm))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run(args.steps)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = elapsed * 1e3 / args.steps
-    value = H * W * V * args.steps / elapsed / 1e6
-    fl_bad = sum(int((m != M).sum().item()) for m in fl_Ms)  # against the single-stream masks
-    for c in fl_ctxs:
-        c.occl_release()
-
-    def step():
-        ctx.occl_detect(D, sc.angles, sc.ratios, prm, M=M)
-
-    # per-kernel durations: the same steps again with HIP events between stages
-    ctx.occl_profile_enable(True)
-    for _ in range(args.steps):
-        step()
-    prof = ctx.occl_profile_read()
-    ctx.occl_profile_enable(False)
-    n_cand = ctx.occl_last_candidate_counts(V)
-    edge_ms = prof["edges"][0] / max(1, prof["edges"][1])
-    scan_ms = prof["scanlines"][0] / max(1, prof["scanlines"][1])
-    # the scanline pass alone, re-run back to back between two events on its
-    # stream (an event pair around each single launch adds the dispatch gap)
-    scan_ms_rep = ctx.occl_time_scanlines(args.steps)
-
-    workload = f"c1 {W}x{H} x{V} views seed {args.seed}"
-    alg_bytes = (4 + V) * H * W                       # D read once + every mask byte written once
-    path_gbps = alg_bytes / (ms_per_step * 1e-3) / 1e9
-    if scan_ms >= edge_ms:
-        ops = scanline_ops(n_cand, sc.scan_len, sc.params["neighbours"])
-        achieved = ops / (scan_ms_rep * 1e-3) / 1e9
-        ks = scan_kernels(sc.scan_len)  # one launch per class; c1 has one
-        roof = {"kernel": ks[0] if len(ks) == 1 else "k_scanlines", "bound": "alu",
-                "achieved": round(achieved, 2), "peak": ALU_PEAK_GOPS, "unit": "Gop/s",
-                "frac": round(achieved / ALU_PEAK_GOPS, 5),
-                "traffic": traffic_for(ks[0], workload) if len(ks) == 1 else None,
-                "avg_ms": round(scan_ms_rep, 5), "avg_ms_event_pair_per_step": round(scan_ms, 5),
-                "ops_per_launch": ops}
-    else:
-        achieved = alg_bytes / (edge_ms * 1e-3) / 1e9
-        roof = {"kernel": "k_edges<0>", "bound": "hbm", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                "traffic": traffic_for("k_edges<0>", workload), "avg_ms": round(edge_ms, 5),
-                "bytes_per_launch": alg_bytes}
-
+    ctx = occl.Context(0)
+    c3 = bench_c3(ctx, args)
+    frames = c3.pop("frames")
+    c3.pop("masks")
+    sizes = sorted({(f.W, f.H) for f in frames})
     out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "Mpixel-views/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
+        "metric": METRIC, "value": round(c3["value"], 1), "unit": "Mpixel-views/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(c3["ms_per_step"], 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": workload, "frame": f"{W}x{H}", "views": V,
-                   "scan_len": [int(x) for x in sc.scan_len], "path": "exact",
-                   "parallelism": "single GPU", "frames_in_flight": S,
-                   "in_flight_launch_shape": fl_shape},
-        "prewarm_steps": max(args.warmup, args.prewarm),
-        "single_stream": {"ms_per_step": round(single_ms, 5),
-                          "value": round(H * W * V / (single_ms * 1e-3) / 1e6, 1),
-                          "note": "one frame at a time: per-frame latency"},
-        "roofline": roof,
-        "hbm": {"alg_bytes_per_step": alg_bytes, "path_gbps": round(path_gbps, 1),
-                "path_frac": round(path_gbps / HBM_PEAK_GBPS, 4)},
-        "stages_ms": {"edges": round(edge_ms, 5), "scanlines": round(scan_ms, 5)},
-        "launch_shape": tune,
-        "candidates_per_view": [int(x) for x in n_cand],
+        "config": {"workload": "c3: 64 frames of mixed size, 8 views each, seed 3000, one batched "
+                               "graph launch per step",
+                   "frames": len(frames), "frame_sizes": [f"{w}x{h}" for w, h in sizes],
+                   "views": 8, "pixel_views_per_step": c3["pixel_views"], "path": "exact",
+                   "parallelism": "single GPU", "launch_shape": c3["launch_shape"]},
+        "prewarm_steps": max(args.warmup, args.prewarm_batched),
+        "frames_per_s": round(len(frames) / (c3["ms_per_step"] * 1e-3), 1),
+        "roofline": c3["roofline"],
+        "hbm": {"alg_bytes_per_step": c3["alg_bytes"],
+                "path_gbps": round(c3["alg_bytes"] / (c3["ms_per_step"] * 1e-3) / 1e9, 1),
+                "path_frac": round(c3["alg_bytes"] / (c3["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)},
+        "stages_ms": {k: round(v, 5) for k, v in c3["stages_ms"].items()},
     }
+    for k in ("parity", "alu"):
+        if k in c3:
+            out[k] = c3[k]
 
-    if not args.no_check:
-        from oracle import occl_ref
-        M_ref, _, nc_ref = occl_ref.detect_scene(sc)
-        bad = int((M.cpu().numpy() != M_ref).sum())
-        out["parity"] = {"mismatches": bad, "candidates_equal": bool(np.array_equal(n_cand, nc_ref)),
-                         "frames_in_flight_disagreeing_bytes": fl_bad}
+    if not args.no_c1:
+        out["c1"] = bench_c1(args)
+
+    if not args.no_c2:
+        out["c2"] = bench_c2(ctx, args.c2_steps, not args.no_tune)
 
     if not args.no_context:
         # the shape of the paper's runtime experiment (Table 3), as context only
@@ -740,11 +898,14 @@ def main() -> int:
             "paper_gpu_ms": 26.0, "paper_gpu_value": round(PAPER_GPU_MPVS, 1),
             "paper_hw": "NVIDIA GeForce RTX 3090 (paper's own scene, not this one)"}
 
-    if not args.no_batched:
-        out["batched"] = bench_batched(ctx, args.batched_steps, not args.no_tune)
-
     if not args.no_learned:
         out["learned"] = bench_learned(ctx, args.learned_steps, args.learned_eval)
+        ex = out["learned"]["exact"]
+        pv4 = 1920 * 1080 * 8
+        out["c4_exact"] = {"workload": "c4 1920x1080 x8 views, c1 statistics, seed 4100",
+                           "ms": ex["ms"], "value": ex["mpixel_views_per_s"],
+                           "hbm_frac": round((4 + 8) * pv4 / 8 / (ex["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                           "stages_ms": ex["stages_ms"]}
 
     if not args.no_quality:
         out["quality_vs_zbuffer"] = bench_quality(ctx)
@@ -752,7 +913,7 @@ def main() -> int:
         out["thinning"] = bench_thin(ctx, args.seed)
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(frames, args.cpu_seconds)
 
     ctx.occl_release()
     print(json.dumps(out), flush=True)

@@ -107,12 +107,23 @@ typedef struct {
 void occl_params_default(occl_params* p);
 
 /* Creates a context on HIP device `device`.  `hip_stream` is the hipStream_t
- * every call of this context is enqueued on (NULL: the device's default
- * stream).  All work is enqueued on that stream; the library's own two
- * streams serve only to capture the batched launch's graph.  The hints size
- * the initial workspace (0: grow on first use). */
+ * every call of this context is enqueued on; NULL: the context creates a
+ * stream of its own (default priority, ordered with the device's null
+ * stream like any blocking stream) and destroys it in occl_release.  All work
+ * is enqueued on that stream; the library's other streams serve only to
+ * capture the batched launch's graph.  The hints size the initial workspace
+ * (0: grow on first use).  The context owns its workspaces, tuned launch
+ * shapes, graphs and network state. */
 occl_status occl_init(occl_ctx** out, int device, void* hip_stream, size_t max_pixels_hint,
                       int32_t max_views_hint);
+
+/* Upper bound on the device memory the context's workspaces may hold in total
+ * (bytes; 0 = unlimited, the default).  A call whose workspace would grow
+ * beyond it returns OCCL_ERR_OUT_OF_MEMORY before anything is enqueued; what
+ * is already allocated stays.  occl_workspace_bytes reports the current
+ * total. */
+occl_status occl_set_workspace_cap(occl_ctx* ctx, size_t bytes);
+occl_status occl_workspace_bytes(const occl_ctx* ctx, size_t* bytes);
 
 /* One frame, n_views views.
  *   D          device fp32 [H][W], row-major contiguous (16-byte alignment and W % 4 == 0
@@ -186,6 +197,14 @@ occl_status occl_edges(occl_ctx* ctx, const float* D, int32_t H, int32_t W, floa
  * out host uint64[4] = {TP, FP, FN, TN}; synchronises the stream. */
 occl_status occl_confusion(occl_ctx* ctx, const uint8_t* pred, const uint8_t* ref, int64_t n,
                            uint64_t* out);
+
+/* Quality of pred against ref by Eq. (7): out host double[4] = {precision
+ * TP/(TP+FP), recall TP/(TP+FN), F1 = 2PR/(P+R), IoU TP/(TP+FP+FN)} from the
+ * counts of occl_confusion (a ratio with a zero denominator is 1; F1 with
+ * P = R = 0 is 0); counts (host uint64[4], may be NULL) receives {TP, FP, FN,
+ * TN}.  Synchronises the stream. */
+occl_status occl_quality(occl_ctx* ctx, const uint8_t* pred, const uint8_t* ref, int64_t n,
+                         double* out, uint64_t* counts);
 
 /* ---- learned tile proposal + exact fallback -------------------------------
  * Not part of the paper: a small network proposes, per 16 x 16 pixel tile
@@ -328,6 +347,16 @@ occl_status occl_profile_read(occl_ctx* ctx, double* ms /* [OCCL_N_STAGES] */,
  * after occl_detect).  OCCL_ERR_STATE when there is no such frame or the
  * context's list workspace has been reallocated since. */
 occl_status occl_time_scanlines(occl_ctx* ctx, int32_t reps, double* ms_per_pass);
+
+/* Stage timing of the most recent occl_detect_batched call: its kernels
+ * re-enqueued `reps` times outside the graph, on the context's stream (the
+ * graph's branches one after the other), with HIP events around the edge
+ * stage (Eqs. (1)-(2), mask clear, per-frame prefix) and the scanline stage
+ * (Eqs. (4)-(6)); ms (host double[2]) receives the mean milliseconds per
+ * batch of each.  The masks are rewritten with the same values.  The
+ * frames' D and M must still be valid.  Synchronises.  OCCL_ERR_STATE when
+ * there is no such batch or its frame table has been reallocated since. */
+occl_status occl_time_batched(occl_ctx* ctx, int32_t reps, double* ms);
 
 const char* occl_status_string(occl_status s);
 const char* occl_last_error(const occl_ctx* ctx);

@@ -203,10 +203,20 @@ extern "C" occl_status occl_init(occl_ctx** out, int device, void* hip_stream,
     occl_ctx* ctx = new (std::nothrow) occl_ctx();
     if (!ctx) return OCCL_ERR_OUT_OF_MEMORY;
     ctx->device = device;
-    // NULL is the device's default (null) stream, which orders itself with
-    // every blocking stream of the process (torch's default stream is it).
+    // NULL: the context creates and owns a stream of its own (default
+    // priority; blocking, so it still orders itself with the device's null
+    // stream), destroyed by occl_release.
     ctx->stream = (hipStream_t)hip_stream;
     ctx->own_stream = false;
+    if (!ctx->stream) {
+        if (hipStreamCreate(&ctx->stream) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->stream = nullptr;
+            delete ctx;
+            return OCCL_ERR_HIP;
+        }
+        ctx->own_stream = true;
+    }
     if (hipHostMalloc((void**)&ctx->host_stats, 64, hipHostMallocDefault) != hipSuccess) {
         ctx->host_stats = nullptr;
         delete ctx;
@@ -227,6 +237,18 @@ extern "C" occl_status occl_init(occl_ctx** out, int device, void* hip_stream,
         return s;
     }
     *out = ctx;
+    return OCCL_OK;
+}
+
+extern "C" occl_status occl_set_workspace_cap(occl_ctx* ctx, size_t bytes) {
+    if (!ctx) return OCCL_ERR_INVALID_ARG;
+    ctx->workspace_cap = bytes;
+    return OCCL_OK;
+}
+
+extern "C" occl_status occl_workspace_bytes(const occl_ctx* ctx, size_t* bytes) {
+    if (!ctx || !bytes) return OCCL_ERR_INVALID_ARG;
+    *bytes = ctx->total_bytes();
     return OCCL_OK;
 }
 
@@ -670,5 +692,26 @@ extern "C" occl_status occl_confusion(occl_ctx* ctx, const uint8_t* pred, const 
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return ctx->hip_fail(e, "confusion readback");
     std::memcpy(out, ctx->host_stats, 4 * sizeof(uint64_t));
+    return OCCL_OK;
+}
+
+// Eq. (7): precision TP / (TP + FP), recall TP / (TP + FN), their harmonic
+// mean F1 and IoU TP / (TP + FP + FN) of pred against ref, in double from
+// the integer counts.  A ratio whose denominator is 0 has no errors to
+// count and is 1 (F1 of P = R = 0 is 0).
+extern "C" occl_status occl_quality(occl_ctx* ctx, const uint8_t* pred, const uint8_t* ref, int64_t n,
+                                    double* out, uint64_t* counts) {
+    if (!ctx || !out) return OCCL_ERR_INVALID_ARG;
+    uint64_t c[4];
+    occl_status s = occl_confusion(ctx, pred, ref, n, c);
+    if (s != OCCL_OK) return s;
+    const double tp = (double)c[0], fp = (double)c[1], fn = (double)c[2];
+    const double P = (c[0] + c[1]) ? tp / (tp + fp) : 1.0;
+    const double R = (c[0] + c[2]) ? tp / (tp + fn) : 1.0;
+    out[0] = P;
+    out[1] = R;
+    out[2] = (P + R > 0.0) ? 2.0 * P * R / (P + R) : 0.0;
+    out[3] = (c[0] + c[1] + c[2]) ? tp / (tp + fp + fn) : 1.0;
+    if (counts) std::memcpy(counts, c, sizeof c);
     return OCCL_OK;
 }

@@ -227,6 +227,70 @@ occl_status occl_ctx::enqueue_batch(int n_frames, const occl_frame* frames, int 
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     prof_end(OCCL_STAGE_BATCHED, ev);
     ++graph_launches;
+    LastBatch& lb = last_batch;
+    lb.valid = true;
+    lb.table = (const FrameDesc*)table;
+    lb.n_branches = nb;
+    lb.n_views = n_views;
+    lb.edge_rows = tc.edge_rows;
+    lb.edge_grid = sg.edge_grid;
+    lb.scan_grid = sg.scan_grid;
+    for (int b = 0; b <= nb; ++b) {
+        lb.cut[b] = cut[b];
+        lb.bstart[b] = bstart[b];
+        if (b < nb) lb.cls_mask[b] = cls_mask[b];
+    }
+    lb.vt = vt;
+    lb.th = th;
+    return OCCL_OK;
+}
+
+// Stage timing of the most recent batch: its kernels re-enqueued eagerly on
+// the context's stream (the graph's branches one after the other), `reps`
+// times, with HIP events around the edge stage (edge pass + per-frame
+// prefix) and the scanline stage of every repetition.  Re-running the
+// sequence rewrites the same masks.
+extern "C" occl_status occl_time_batched(occl_ctx* ctx, int32_t reps, double* ms) {
+    if (!ctx || !ms || reps < 1) return OCCL_ERR_INVALID_ARG;
+    const occl_ctx::LastBatch& lb = ctx->last_batch;
+    auto tb = ctx->bufs.find("btable");
+    if (!lb.valid || tb == ctx->bufs.end() || tb->second.ptr != (const void*)lb.table)
+        return ctx->fail(OCCL_ERR_STATE, "no batch to re-time");
+    (void)hipSetDevice(ctx->device);
+    hipEvent_t ev[3] = {ctx->take_event(), ctx->take_event(), ctx->take_event()};
+    for (hipEvent_t x : ev)
+        if (!x) {
+            for (hipEvent_t y : ev)
+                if (y) ctx->ev_pool.push_back(y);
+            return ctx->fail(OCCL_ERR_HIP, "hipEventCreate(time_batched)");
+        }
+    double acc[2] = {0.0, 0.0};
+    hipError_t e = hipSuccess;
+    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+        e = hipEventRecord(ev[0], ctx->stream);
+        for (int b = 0; b < lb.n_branches && e == hipSuccess; ++b) {
+            const int nf = lb.cut[b + 1] - lb.cut[b], blocks = lb.bstart[b + 1] - lb.bstart[b];
+            e = launch_edges_batched(ctx->stream, lb.table + lb.cut[b], nf, blocks, lb.n_views, lb.vt,
+                                     lb.th.q_min, lb.edge_rows, std::min(blocks, lb.edge_grid));
+        }
+        if (e == hipSuccess) e = hipEventRecord(ev[1], ctx->stream);
+        for (int b = 0; b < lb.n_branches && e == hipSuccess; ++b)
+            for (int ci = 0; ci < kNumClasses && e == hipSuccess; ++ci)
+                if (lb.cls_mask[b] & (1u << ci))
+                    e = launch_scanlines_batched(ctx->stream, lb.table + lb.cut[b], lb.cut[b + 1] - lb.cut[b],
+                                                 lb.n_views, lb.vt, lb.th, ci, lb.scan_grid);
+        if (e == hipSuccess) e = hipEventRecord(ev[2], ctx->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[2]);
+        float t0 = 0.0f, t1 = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t0, ev[0], ev[1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t1, ev[1], ev[2]);
+        acc[0] += t0;
+        acc[1] += t1;
+    }
+    for (hipEvent_t x : ev) ctx->ev_pool.push_back(x);
+    if (e != hipSuccess) return ctx->hip_fail(e, "time_batched");
+    ms[0] = acc[0] / reps;
+    ms[1] = acc[1] / reps;
     return OCCL_OK;
 }
 

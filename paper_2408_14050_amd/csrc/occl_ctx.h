@@ -62,6 +62,17 @@ struct occl_ctx {
     };
     std::vector<GraphEntry> graphs;         // most recent first
     int64_t graph_builds = 0, graph_launches = 0;
+    // the most recent batch's launch sequence (occl_time_batched re-runs it)
+    struct LastBatch {
+        bool valid = false;
+        const occl::FrameDesc* table = nullptr;  // device frame table
+        int n_branches = 0, n_views = 0, edge_rows = 0, edge_grid = 0, scan_grid = 0;
+        int cut[occl::kMaxBatchBranches + 1] = {};
+        int bstart[occl::kMaxBatchBranches + 1] = {};
+        unsigned cls_mask[occl::kMaxBatchBranches] = {};
+        occl::ViewTable vt{};
+        occl::Thresholds th{};
+    } last_batch;
 
     // learned tile proposal (k_cnn.hip); weights, Adam moments and
     // activations live in `bufs`

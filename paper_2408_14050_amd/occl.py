@@ -77,6 +77,10 @@ _SIGS = {
                                       C.POINTER(occl_params)]),
     "occl_last_candidate_counts": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_int32]),
     "occl_edges": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
+    "occl_quality": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                               C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
+    "occl_set_workspace_cap": (C.c_int, [C.c_void_p, C.c_size_t]),
+    "occl_workspace_bytes": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "occl_confusion": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                  C.POINTER(C.c_uint64)]),
     "occl_zbuffer": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
@@ -90,6 +94,7 @@ _SIGS = {
     "occl_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "occl_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "occl_time_scanlines": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
+    "occl_time_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
     "occl_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
                                 C.POINTER(C.c_double), C.POINTER(C.c_float), C.POINTER(occl_params),
                                 C.c_void_p, C.c_int32, C.POINTER(occl_tune)]),
@@ -173,6 +178,39 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def check_tensor(t, name: str, dtype, shape=None, dim=None, device=None):
+    """Raises ValueError unless `t` is a contiguous tensor of `dtype` (with
+    `dim` dimensions and the given `shape` where stated) on ROCm device
+    `device`.  The C ABI receives a bare device pointer and assumes exactly
+    that layout: a strided view, another dtype, a host tensor or a short
+    buffer would be misread or written out of bounds."""
+    if t is None:
+        raise ValueError(f"{name} is None")
+    if dim is not None and t.dim() != dim:
+        raise ValueError(f"{name} must have {dim} dimensions, got shape {tuple(t.shape)}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(int(x) for x in t.shape) != tuple(int(x) for x in shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous (row-major, no strides)")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a ROCm device tensor, got device {t.device}")
+    if device is not None and t.device.index != int(device):
+        raise ValueError(f"{name} is on device {t.device.index}, the context on {device}")
+    return t
+
+
+def check_frame(D, M, n_views: int, device=None):
+    """D float32 [H, W] and M uint8 [n_views, H, W], both contiguous on the
+    context's device (the layout occl_detect reads and writes)."""
+    import torch
+    check_tensor(D, "D", torch.float32, dim=2, device=device)
+    H, W = int(D.shape[0]), int(D.shape[1])
+    check_tensor(M, "M", torch.uint8, shape=(n_views, H, W), device=device)
+    return H, W
+
+
 class Context:
     """An occl_ctx bound to one ROCm device and one HIP stream."""
 
@@ -210,9 +248,11 @@ class Context:
         """D: float32 [H, W] device tensor; returns M uint8 [V, H, W]."""
         torch = self._torch
         a, r = self._views(angles, ratios)
-        H, W = (int(D.shape[0]), int(D.shape[1])) if D.dim() == 2 else (0, 0)
+        check_tensor(D, "D", torch.float32, dim=2, device=self.device)
+        H, W = int(D.shape[0]), int(D.shape[1])
         if M is None:
             M = torch.empty((a.shape[0], H, W), dtype=torch.uint8, device=D.device)
+        check_frame(D, M, int(a.shape[0]), self.device)
         st = lib().occl_detect(self.h, _ptr(D), H, W, int(a.shape[0]),
                                a.ctypes.data_as(C.POINTER(C.c_double)),
                                r.ctypes.data_as(C.POINTER(C.c_float)), C.byref(prm), _ptr(M))
@@ -229,8 +269,13 @@ class Context:
         pr = C.byref(prm)
         L, h, nv = lib(), self.h, int(a.shape[0])
         keep = (a, r, prm)
+        seen = [None]  # the last (D, M) pair that passed the checks
 
         def detect(D, M):
+            key = (D.data_ptr(), M.data_ptr(), tuple(D.shape), tuple(M.shape), D.dtype, M.dtype)
+            if key != seen[0]:
+                check_frame(D, M, nv, self.device)
+                seen[0] = key
             st = L.occl_detect(h, C.c_void_p(D.data_ptr()), int(D.shape[0]), int(D.shape[1]), nv,
                                ap, rp, pr, C.c_void_p(M.data_ptr()))
             if st != OCCL_OK:
@@ -240,11 +285,11 @@ class Context:
         detect._keep = keep  # the marshalled arrays live as long as the function
         return detect
 
-    @staticmethod
-    def _frames(frames):
+    def _frames(self, frames, n_views):
         arr = (occl_frame * max(1, len(frames)))()
         keep = []
         for i, (D, M, Ls) in enumerate(frames):
+            check_frame(D, M, n_views, self.device)
             arr[i].D = D.data_ptr()
             arr[i].H, arr[i].W = int(D.shape[0]), int(D.shape[1])
             arr[i].M = M.data_ptr()
@@ -257,7 +302,7 @@ class Context:
     def occl_detect_batched(self, frames, angles, ratios, prm: occl_params):
         """frames: list of (D, M, scan_len_per_view or None)."""
         a, r = self._views(angles, ratios)
-        arr, keep = self._frames(frames)
+        arr, keep = self._frames(frames, int(a.shape[0]))
         st = lib().occl_detect_batched(self.h, len(frames), arr, int(a.shape[0]),
                                        a.ctypes.data_as(C.POINTER(C.c_double)),
                                        r.ctypes.data_as(C.POINTER(C.c_float)), C.byref(prm))
@@ -265,6 +310,7 @@ class Context:
 
     def occl_autotune(self, D, angles, ratios, prm: occl_params, M, reps: int = 10):
         a, r = self._views(angles, ratios)
+        check_frame(D, M, int(a.shape[0]), self.device)
         out = occl_tune()
         st = lib().occl_autotune(self.h, _ptr(D), int(D.shape[0]), int(D.shape[1]), int(a.shape[0]),
                                  a.ctypes.data_as(C.POINTER(C.c_double)),
@@ -275,7 +321,7 @@ class Context:
 
     def occl_autotune_batched(self, frames, angles, ratios, prm: occl_params, reps: int = 5):
         a, r = self._views(angles, ratios)
-        arr, keep = self._frames(frames)
+        arr, keep = self._frames(frames, int(a.shape[0]))
         out = occl_tune()
         st = lib().occl_autotune_batched(self.h, len(frames), arr, int(a.shape[0]),
                                          a.ctypes.data_as(C.POINTER(C.c_double)),
@@ -298,11 +344,19 @@ class Context:
         return out
 
     def occl_edges(self, D, E=None, A=None):
+        torch = self._torch
+        check_tensor(D, "D", torch.float32, dim=2, device=self.device)
+        for name, t in (("E", E), ("A", A)):
+            if t is not None:
+                check_tensor(t, name, torch.float32, shape=D.shape, device=self.device)
         st = lib().occl_edges(self.h, _ptr(D), int(D.shape[0]), int(D.shape[1]), _ptr(E), _ptr(A))
         self._check(st, "occl_edges")
         return E, A
 
     def occl_confusion(self, pred, ref):
+        torch = self._torch
+        check_tensor(pred, "pred", torch.uint8, device=self.device)
+        check_tensor(ref, "ref", torch.uint8, shape=pred.shape, device=self.device)
         out = np.zeros(4, np.uint64)
         st = lib().occl_confusion(self.h, _ptr(pred), _ptr(ref), int(pred.numel()),
                                   out.ctypes.data_as(C.POINTER(C.c_uint64)))
@@ -313,9 +367,11 @@ class Context:
         """Forward-warping ground truth masks uint8 [V, H, W] (Eq. (7) reference)."""
         torch = self._torch
         a, r = self._views(angles, ratios)
+        check_tensor(D, "D", torch.float32, dim=2, device=self.device)
         H, W = int(D.shape[0]), int(D.shape[1])
         if M is None:
             M = torch.empty((a.shape[0], H, W), dtype=torch.uint8, device=D.device)
+        check_frame(D, M, int(a.shape[0]), self.device)
         st = lib().occl_zbuffer(self.h, _ptr(D), H, W, int(a.shape[0]),
                                 a.ctypes.data_as(C.POINTER(C.c_double)),
                                 r.ctypes.data_as(C.POINTER(C.c_float)), float(beta), _ptr(M))
@@ -325,21 +381,36 @@ class Context:
     def occl_median_fuse(self, maps, D=None):
         """maps: float32 [K, H, W] device tensor -> fused D [H, W] (NaN-ignoring median)."""
         torch = self._torch
+        check_tensor(maps, "maps", torch.float32, dim=3, device=self.device)
         K, H, W = int(maps.shape[0]), int(maps.shape[1]), int(maps.shape[2])
         if D is None:
             D = torch.empty((H, W), dtype=torch.float32, device=maps.device)
+        check_tensor(D, "D", torch.float32, shape=(H, W), device=self.device)
         st = lib().occl_median_fuse(self.h, _ptr(maps), K, H, W, _ptr(D))
         self._check(st, "occl_median_fuse")
         return D
 
     def occl_quality(self, pred, ref):
-        """Eq. (7) on the GPU counts: precision, recall, F1, IoU (pooled)."""
-        c = self.occl_confusion(pred, ref)
-        tp, fp, fn = c["tp"], c["fp"], c["fn"]
-        P = tp / (tp + fp) if tp + fp else 1.0
-        R = tp / (tp + fn) if tp + fn else 1.0
-        return {"precision": P, "recall": R, "f1": 2 * P * R / (P + R) if P + R else 0.0,
-                "iou": tp / (tp + fp + fn) if tp + fp + fn else 1.0, **c}
+        """Eq. (7) from the library: precision, recall, F1, IoU and the counts."""
+        torch = self._torch
+        check_tensor(pred, "pred", torch.uint8, device=self.device)
+        check_tensor(ref, "ref", torch.uint8, shape=pred.shape, device=self.device)
+        q = np.zeros(4, np.float64)
+        c = np.zeros(4, np.uint64)
+        st = lib().occl_quality(self.h, _ptr(pred), _ptr(ref), int(pred.numel()),
+                                q.ctypes.data_as(C.POINTER(C.c_double)),
+                                c.ctypes.data_as(C.POINTER(C.c_uint64)))
+        self._check(st, "occl_quality")
+        return {"precision": float(q[0]), "recall": float(q[1]), "f1": float(q[2]), "iou": float(q[3]),
+                "tp": int(c[0]), "fp": int(c[1]), "fn": int(c[2]), "tn": int(c[3])}
+
+    def occl_set_workspace_cap(self, nbytes: int):
+        self._check(lib().occl_set_workspace_cap(self.h, int(nbytes)), "occl_set_workspace_cap")
+
+    def occl_workspace_bytes(self) -> int:
+        n = C.c_size_t()
+        self._check(lib().occl_workspace_bytes(self.h, C.byref(n)), "occl_workspace_bytes")
+        return int(n.value)
 
     def occl_profile_enable(self, enable: bool = True):
         self._check(lib().occl_profile_enable(self.h, int(bool(enable))), "occl_profile_enable")
@@ -360,15 +431,29 @@ class Context:
         self._check(lib().occl_time_scanlines(self.h, int(reps), C.byref(ms)), "occl_time_scanlines")
         return ms.value
 
+    def occl_time_batched(self, reps: int = 20):
+        """Mean ms per batch of the edge stage and the scanline stage of the
+        last occl_detect_batched, re-run `reps` times outside the graph."""
+        ms = np.zeros(2, np.float64)
+        self._check(lib().occl_time_batched(self.h, int(reps), ms.ctypes.data_as(C.POINTER(C.c_double))),
+                    "occl_time_batched")
+        return {"edges": float(ms[0]), "scanlines": float(ms[1])}
+
     def occl_detect_routed(self, D, angles, ratios, prm: occl_params, logits, M=None,
                            tile_state=None):
         """Exact path on the tiles the logits leave uncertain; fills the rest.
         logits: float32 [V, ceil(H/16), ceil(W/16)] device tensor."""
         torch = self._torch
         a, r = self._views(angles, ratios)
+        check_tensor(D, "D", torch.float32, dim=2, device=self.device)
         H, W = int(D.shape[0]), int(D.shape[1])
         if M is None:
             M = torch.empty((a.shape[0], H, W), dtype=torch.uint8, device=D.device)
+        check_frame(D, M, int(a.shape[0]), self.device)
+        tshape = (int(a.shape[0]), (H + 15) // 16, (W + 15) // 16)
+        check_tensor(logits, "logits", torch.float32, shape=tshape, device=self.device)
+        if tile_state is not None:
+            check_tensor(tile_state, "tile_state", torch.uint8, shape=tshape, device=self.device)
         st = lib().occl_detect_routed(self.h, _ptr(D), H, W, int(a.shape[0]),
                                       a.ctypes.data_as(C.POINTER(C.c_double)),
                                       r.ctypes.data_as(C.POINTER(C.c_float)), C.byref(prm),
@@ -408,6 +493,7 @@ class Context:
         torch = self._torch
         a, r = self._views(angles, ratios)
         Ls = np.ascontiguousarray(np.atleast_1d(scan_len), dtype=np.int32)
+        check_tensor(D, "D", torch.float32, dim=2, device=self.device)
         H, W = int(D.shape[0]), int(D.shape[1])
         if X is None:
             X = torch.empty((a.shape[0], H, W, 8), dtype=torch.int16, device=D.device)
@@ -432,6 +518,7 @@ class Context:
         torch = self._torch
         a, r = self._views(angles, ratios)
         Ls = np.ascontiguousarray(np.atleast_1d(scan_len), dtype=np.int32)
+        check_tensor(D, "D", torch.float32, dim=2, device=self.device)
         H, W = int(D.shape[0]), int(D.shape[1])
         if Z is None:
             Z = torch.empty((a.shape[0], (H + 15) // 16, (W + 15) // 16), dtype=torch.float32,
