@@ -378,3 +378,75 @@ def fusion_maps(seed: int, D: np.ndarray, K: int = 8, noise: float = 0.3, outlie
     maps[out] = rng.uniform(0.0, 2.0 * float(D.max()) + 1.0, size=int(out.sum())).astype(np.float32)
     maps[rng.uniform(size=maps.shape) < holes] = np.nan
     return np.ascontiguousarray(maps, dtype=np.float32)
+
+
+# ---------------------------------------------------------------------------
+# the limitation cases of Sec. 5, with every painted surface kept
+# ---------------------------------------------------------------------------
+@dataclass
+class Layer:
+    """One painted surface: its pixels in centre-view coordinates (they may
+    lie outside the centre frame) and their disparities, including the parts
+    that nearer surfaces hide in the centre view."""
+    name: str
+    x: np.ndarray   # int64
+    y: np.ndarray   # int64
+    d: np.ndarray   # float32
+
+
+def _rect_layer(name, x0, x1, y0, y1, d) -> Layer:
+    yy, xx = np.mgrid[y0:y1, x0:x1]
+    return Layer(name, xx.ravel().astype(np.int64), yy.ravel().astype(np.int64),
+                 np.full(xx.size, d, np.float32))
+
+
+LIMITATION_CASES = ("occluded_occluder", "outside_border", "one_camera")
+
+
+def limitation_scene(kind: str):
+    """A small scene for one limitation of the method (Sec. 5) and the list
+    of every surface painted into it.  The visible centre map D is what the
+    painter's algorithm leaves in the frame (ascending disparity, nearer
+    surfaces overwrite farther ones); surfaces outside the frame, and the
+    hidden parts of overwritten ones, are in the layers only.
+
+    Every scene is in the class where the method equals a forward-warping
+    z-buffer of D exactly: integer fronto-parallel layers, views at 0 and
+    180 degrees with r = 1, zeta = 1, beta = 0.5, N = 1 and
+    L = 2 (max D - min D) + 4 (the layers outside D included).
+
+    occluded_occluder  a plate (d 10) whose left four columns sit behind a
+                       thin pole (d 30): in the right camera (0 degrees)
+                       the hidden columns cover background that D cannot
+                       explain.
+    outside_border     an object (d 20) just right of the frame: in the
+                       right camera it covers background inside the frame.
+    one_camera         an object very close to the cameras (d 60), outside
+                       the centre camera's frame and seen only by the right
+                       camera.
+    All three also hold an ordinary object inside the frame."""
+    H, W = 96, 160
+    bg = 2.0
+    layers = [_rect_layer("background", -96, W + 96, -8, H + 8, bg)]
+    if kind == "occluded_occluder":
+        layers += [_rect_layer("object", 20, 40, 30, 60, 8.0),
+                   _rect_layer("plate", 90, 130, 20, 70, 10.0),
+                   _rect_layer("pole", 90, 94, 10, 80, 30.0)]
+    elif kind == "outside_border":
+        layers += [_rect_layer("object", 40, 70, 20, 50, 8.0),
+                   _rect_layer("outside", W, W + 6, 30, 60, 20.0)]
+    elif kind == "one_camera":
+        layers += [_rect_layer("object", 40, 70, 20, 50, 8.0),
+                   _rect_layer("near", W + 30, W + 40, 10, 50, 60.0)]
+    else:
+        raise ValueError(f"unknown limitation case {kind!r}")
+    D = np.zeros((H, W), np.float32)
+    for ly in sorted(layers, key=lambda l: float(l.d.max())):  # painter's algorithm
+        inside = (ly.x >= 0) & (ly.x < W) & (ly.y >= 0) & (ly.y < H)
+        D[ly.y[inside], ly.x[inside]] = ly.d[inside]
+    dmax = max(float(l.d.max()) for l in layers)
+    L = int(2 * (dmax - bg) + 4)
+    params = dict(edge_thr=1.0, disp_thr=0.5, dist_thr=1.0, neighbours=1)
+    sc = Scene(kind, 0, np.ascontiguousarray(D), np.array([0.0, 180.0]),
+               np.array([1.0, 1.0], np.float32), np.array([L, L], np.int32), params)
+    return sc, layers
