@@ -113,7 +113,8 @@ void occl_params_default(occl_params* p);
  * is enqueued on that stream; the library's other streams serve only to
  * capture the batched launch's graph.  The hints size the initial workspace
  * (0: grow on first use).  The context owns its workspaces, tuned launch
- * shapes, graphs and network state. */
+ * shapes, graphs and network state; it also resolves the address of the
+ * device's static scratch array used by occl_detect_noalloc. */
 occl_status occl_init(occl_ctx** out, int device, void* hip_stream, size_t max_pixels_hint,
                       int32_t max_views_hint);
 
@@ -138,6 +139,32 @@ occl_status occl_workspace_bytes(const occl_ctx* ctx, size_t* bytes);
 occl_status occl_detect(occl_ctx* ctx, const float* D, int32_t H, int32_t W, int32_t n_views,
                         const double* angles_deg, const float* ratios, const occl_params* params,
                         uint8_t* M);
+
+/* ---- the exact path without device allocation ----------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * occl_detect_noalloc writes exactly the masks occl_detect writes (the same
+ * kernels and launch shape) but takes the frame's workspace (candidate
+ * lists, counters, prefix, statistics partials) from a static device array
+ * of OCCL_NOALLOC_SCRATCH_BYTES that the library holds on every device it
+ * runs on until the process ends; its address is resolved by occl_init.
+ * The call itself allocates nothing: no hipMalloc, hipFree or allocating
+ * library routine.
+ * Limits: the candidate lists need about 4 * n_views * H * W bytes (plus
+ * 160 KiB of counters): a 1280 x 960 frame with 8 views fits; a frame that
+ * does not fit returns OCCL_ERR_UNSUPPORTED (occl_last_error gives both
+ * sizes) with nothing enqueued, except that a scan_len of 0 or -1 first
+ * reads D's statistics (through the array) and synchronises, as occl_detect
+ * does.  OCCL_FLAG_USE_CNN returns OCCL_ERR_UNSUPPORTED.
+ * Sharing: every call on one device uses that device's one array and leaves
+ * its contents there; the counters that must start at zero are cleared at
+ * the start of each call.  Calls that overlap on one device (several
+ * streams or contexts) race: the caller serialises them.
+ * The arguments are those of occl_detect. */
+#define OCCL_NOALLOC_SCRATCH_BYTES (64ull * 1024ull * 1024ull)
+occl_status occl_detect_noalloc(occl_ctx* ctx, const float* D, int32_t H, int32_t W, int32_t n_views,
+                                const double* angles_deg, const float* ratios,
+                                const occl_params* params, uint8_t* M);
 
 /* A frame of a batch: its own size, mask and optionally its own scan lengths
  * (host array [n_views]; NULL: params->scan_len / scan_len_per_view). */

@@ -398,6 +398,12 @@ hipError_t launch_scan_stats(hipStream_t st, const float* D, size_t n, uint32_t*
     return hipGetLastError();
 }
 
+hipError_t launch_fill_u32(hipStream_t st, uint32_t* p, long long n) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for((size_t)n, 256, 1024)), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_edges_out(hipStream_t st, const float* D, int H, int W, float* E, float* A) {
     const size_t n = (size_t)H * W;
     hipLaunchKernelGGL(k_edges_out, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, D, H, W, E, A);

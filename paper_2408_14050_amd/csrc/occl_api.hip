@@ -227,6 +227,13 @@ extern "C" occl_status occl_init(occl_ctx** out, int device, void* hip_stream,
         cus <= 0)
         cus = 256;
     ctx->n_cu = cus;
+    // the address of this device's static scratch array (occl_detect_noalloc),
+    // resolved once per device with the device current
+    occl_status ss = scratch_resolve(device, &ctx->scratch);
+    if (ss != OCCL_OK) {
+        delete ctx;
+        return ss;
+    }
     void* p;
     occl_status s = ctx->ensure_zeroed("counts", kCountsBytes, &p);
     if (s == OCCL_OK && max_pixels_hint > 0 && max_views_hint > 0)
@@ -295,10 +302,13 @@ occl_status occl_ctx::check_params(const occl_params* p, int n_views, const doub
 }
 
 // Reads min / max / non-finite count of D back to the host (synchronises).
-occl_status occl_ctx::d_stats(const float* D, size_t n, float* mn, float* mx, uint32_t* bad) {
-    void* dev;
-    occl_status s = ensure("stats", (3 + 3 * (size_t)kStatsBlocks) * sizeof(uint32_t), &dev);
-    if (s != OCCL_OK) return s;
+occl_status occl_ctx::d_stats(const float* D, size_t n, float* mn, float* mx, uint32_t* bad,
+                              void* stats_ws) {
+    void* dev = stats_ws;
+    if (!dev) {
+        occl_status s = ensure("stats", (3 + 3 * (size_t)kStatsBlocks) * sizeof(uint32_t), &dev);
+        if (s != OCCL_OK) return s;
+    }
     hipError_t e = launch_scan_stats(stream, D, n, (uint32_t*)dev);
     if (e != hipSuccess) return hip_fail(e, "scan_stats");
     e = hipMemcpyAsync(host_stats, dev, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, stream);
@@ -322,7 +332,7 @@ occl_status occl_ctx::d_stats(const float* D, size_t n, float* mn, float* mx, ui
 occl_status occl_ctx::resolve_views(const float* D, int H, int W, int n_views,
                                     const double* angles, const float* ratios,
                                     const occl_params* p, const int32_t* frame_L, ViewTable* vt,
-                                    int* Ls) {
+                                    int* Ls, void* stats_ws) {
     bool need_stats = false;
     for (int v = 0; v < n_views; ++v) {
         int L = frame_L ? frame_L[v] : (p->scan_len_per_view ? p->scan_len_per_view[v] : p->scan_len);
@@ -333,7 +343,7 @@ occl_status occl_ctx::resolve_views(const float* D, int H, int W, int n_views,
     if (need_stats || validate) {
         float mn, mx;
         uint32_t bad;
-        occl_status s = d_stats(D, (size_t)H * W, &mn, &mx, &bad);
+        occl_status s = d_stats(D, (size_t)H * W, &mn, &mx, &bad, stats_ws);
         if (s != OCCL_OK) return s;
         if (bad) return fail(OCCL_ERR_INVALID_ARG, "D holds non-finite values");
         for (int v = 0; v < n_views; ++v) {
@@ -448,35 +458,42 @@ extern "C" occl_status occl_profile_read(occl_ctx* ctx, double* ms, int64_t* lau
 occl_status occl_ctx::enqueue_frame(const float* D, int H, int W, int n_views, const int* Ls,
                                     const ViewTable& vt, const Thresholds& th, uint8_t* M,
                                     const TuneConfig* cfg, const uint8_t* tstate,
-                                    const uint8_t* tnear) {
+                                    const uint8_t* tnear, const FrameWorkspace* ws) {
     int maxcls = 0;
     for (int v = 0; v < n_views; ++v) maxcls = std::max(maxcls, scan_class(Ls[v] / 2, th.thin));
     const TuneConfig tc = cfg ? *cfg : config_for(tune_key(false, (size_t)H * W, n_views, maxcls));
     FrameDesc f;
     describe_frame(&f, D, M, H, W, n_views, Ls, tc.edge_rows, th.thin);
-    void *lists, *counts, *prefix;
-    occl_status s = ensure("lists", f.ll.cap * f.ll.copies * n_views * sizeof(uint32_t), &lists);
-    if (s != OCCL_OK) return s;
-    s = ensure_zeroed("counts", kCountsBytes, &counts);
-    if (s != OCCL_OK) return s;
-    s = ensure("prefix", kPrefixInts * sizeof(int32_t), &prefix);
-    if (s != OCCL_OK) return s;
-    f.lists = (uint32_t*)lists;
-    f.counts = (int32_t*)counts;
-    f.prefix = (int32_t*)prefix;
+    if (ws) {
+        f.lists = ws->lists;
+        f.counts = ws->counts;
+        f.prefix = ws->prefix;
+    } else {
+        void *lists, *counts, *prefix;
+        occl_status s = ensure("lists", list_entries(f, n_views) * sizeof(uint32_t), &lists);
+        if (s != OCCL_OK) return s;
+        s = ensure_zeroed("counts", kCountsBytes, &counts);
+        if (s != OCCL_OK) return s;
+        s = ensure("prefix", kPrefixInts * sizeof(int32_t), &prefix);
+        if (s != OCCL_OK) return s;
+        f.lists = (uint32_t*)lists;
+        f.counts = (int32_t*)counts;
+        f.prefix = (int32_t*)prefix;
+    }
     f.tstate = tstate;
     f.tnear = tnear;
-    hipEvent_t ev = prof_begin(OCCL_STAGE_EDGES);
+    hipEvent_t ev = ws ? nullptr : prof_begin(OCCL_STAGE_EDGES);
     hipError_t e = launch_edges(stream, f, n_views, vt, th.q_min);
     if (e != hipSuccess) return hip_fail(e, "edges");
-    prof_end(OCCL_STAGE_EDGES, ev);
-    ev = prof_begin(OCCL_STAGE_SCANLINES);
+    if (!ws) prof_end(OCCL_STAGE_EDGES, ev);
+    if (!ws) ev = prof_begin(OCCL_STAGE_SCANLINES);
     // one scanline launch per register class present: K <= 2, then 4, 8, 16
     for (int ci = 0; ci < kNumClasses; ++ci) {
         if (f.cls_start[ci + 1] == f.cls_start[ci]) continue;
         e = launch_scanlines(stream, f, n_views, vt, th, ci, tc.scan_blocks_per_cu * n_cu);
         if (e != hipSuccess) return hip_fail(e, "scanlines");
     }
+    if (ws) return OCCL_OK;
     prof_end(OCCL_STAGE_SCANLINES, ev);
     last_frame = f;
     last_views = n_views;

@@ -32,6 +32,8 @@ struct occl_ctx {
     bool own_stream = false;
     std::map<std::string, Buf> bufs;     // named device workspaces, grown on demand
     size_t workspace_cap = 0;            // 0 = unlimited
+    void* scratch = nullptr;             // the device's static scratch array (occl_detect_noalloc),
+                                         // its address resolved by occl_init
     uint32_t* host_stats = nullptr;      // pinned 64-byte staging area for read-backs
     std::string last_error;
     int last_views = 0;
@@ -113,14 +115,20 @@ struct occl_ctx {
 
     occl_status check_params(const occl_params* p, int n_views, const double* angles,
                              const float* ratios);
-    occl_status d_stats(const float* D, size_t n, float* mn, float* mx, uint32_t* bad);
+    // stats_ws: device workspace of (3 + 3 * kStatsBlocks) uint32 (NULL: the context's own)
+    occl_status d_stats(const float* D, size_t n, float* mn, float* mx, uint32_t* bad,
+                        void* stats_ws = nullptr);
     occl_status resolve_views(const float* D, int H, int W, int n_views, const double* angles,
                               const float* ratios, const occl_params* p, const int32_t* frame_L,
-                              occl::ViewTable* vt, int* Ls);
+                              occl::ViewTable* vt, int* Ls, void* stats_ws = nullptr);
+    // ws: the frame's workspace supplied by the caller (NULL: the context's
+    // own buffers, grown on demand); a call with ws records no profiling
+    // events and does not become the context's "most recent frame"
     occl_status enqueue_frame(const float* D, int H, int W, int n_views, const int* Ls,
                               const occl::ViewTable& vt, const occl::Thresholds& th, uint8_t* M,
                               const occl::TuneConfig* cfg, const uint8_t* tstate = nullptr,
-                              const uint8_t* tnear = nullptr);
+                              const uint8_t* tnear = nullptr,
+                              const occl::FrameWorkspace* ws = nullptr);
     occl_status enqueue_batch(int n_frames, const occl_frame* frames, int n_views, const int* Ls_all,
                               const occl::ViewTable& vt, const occl::Thresholds& th,
                               const occl::TuneConfig* cfg);

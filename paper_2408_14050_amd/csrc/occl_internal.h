@@ -130,6 +130,22 @@ struct TuneConfig {
     int scan_blocks_per_cu;  // persistent scanline blocks per compute unit
 };
 
+// Workspace of one frame's exact path: candidate lists (list_entries(f)
+// uint32), the segment and completion counters (kCountsInts int32, all zero
+// between frames) and the class-major prefix (kPrefixInts int32).
+struct FrameWorkspace {
+    uint32_t* lists;
+    int32_t* counts;
+    int32_t* prefix;
+};
+inline size_t list_entries(const FrameDesc& f, int n_views) {
+    return f.ll.cap * (size_t)f.ll.copies * (size_t)n_views;
+}
+
+// Address of this device's static scratch array (occl_noalloc.hip); called
+// by occl_init with `device` current, once per device.
+occl_status scratch_resolve(int device, void** out);
+
 // Fills the fields of a FrameDesc that depend only on sizes and scan lengths
 // (layout, grid, class order); the workspace pointers are set by the caller.
 void describe_frame(FrameDesc* f, const float* D, uint8_t* M, int H, int W, int n_views,
@@ -163,6 +179,9 @@ Thresholds make_thresholds(const occl_params* p);
 // holds 3 + 3 * kStatsBlocks uint32
 constexpr int kStatsBlocks = 1024;
 hipError_t launch_scan_stats(hipStream_t st, const float* D, size_t n, uint32_t* dev);
+
+// p[0 .. n) = 0 (a fill kernel: no memset node ever enters a captured graph)
+hipError_t launch_fill_u32(hipStream_t st, uint32_t* p, long long n);
 
 hipError_t launch_edges_out(hipStream_t st, const float* D, int H, int W, float* E, float* A);
 

@@ -72,6 +72,9 @@ _SIGS = {
     "occl_detect": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
                               C.POINTER(C.c_double), C.POINTER(C.c_float), C.POINTER(occl_params),
                               C.c_void_p]),
+    "occl_detect_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                      C.POINTER(C.c_double), C.POINTER(C.c_float),
+                                      C.POINTER(occl_params), C.c_void_p]),
     "occl_detect_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(occl_frame), C.c_int32,
                                       C.POINTER(C.c_double), C.POINTER(C.c_float),
                                       C.POINTER(occl_params)]),
@@ -257,6 +260,17 @@ class Context:
                                a.ctypes.data_as(C.POINTER(C.c_double)),
                                r.ctypes.data_as(C.POINTER(C.c_float)), C.byref(prm), _ptr(M))
         self._check(st, "occl_detect")
+        return M
+
+    def occl_detect_noalloc(self, D, angles, ratios, prm: occl_params, M):
+        """occl_detect with the workspace in the library's static device
+        array (the call allocates no device memory): M must be given."""
+        a, r = self._views(angles, ratios)
+        H, W = check_frame(D, M, int(a.shape[0]), self.device)
+        st = lib().occl_detect_noalloc(self.h, _ptr(D), H, W, int(a.shape[0]),
+                                       a.ctypes.data_as(C.POINTER(C.c_double)),
+                                       r.ctypes.data_as(C.POINTER(C.c_float)), C.byref(prm), _ptr(M))
+        self._check(st, "occl_detect_noalloc")
         return M
 
     def occl_detect_prepared(self, angles, ratios, prm: occl_params):
