@@ -539,6 +539,13 @@ __device__ __forceinline__ int thin_window(const float* __restrict__ D, int H, i
     return 2 * h + 1 + m;  // offsets t > h are never candidates, so m <= h
 }
 
+template <int K, int G>
+__device__ __forceinline__ void order_test_lds(uint8_t* __restrict__ Mv, int W, TileView tv, int cx, int cy,
+                                               float c, float s, int h, const Thresholds& th,
+                                               const WaveLds& L, int lane, const float (&wk)[K],
+                                               const float (&vk)[K], const uint64_t (&vmask)[K],
+                                               const bool (&kept)[K], const uint32_t (&pofs)[K]);
+
 // One scanline: the n <= 64 K samples of offsets g = -h .. n - 1 - h
 // (n = 2h + 1, or a thinning head's merged window).
 template <int K, int G>
@@ -546,7 +553,6 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
                                          uint8_t* __restrict__ Mv, TileView tv, int cx, int cy, float c,
                                          float s, float r, int h, int n, const Thresholds& th,
                                          const WaveLds& L, int lane) {
-    constexpr int N = 64 * K;
     float wk[K], vk[K];  // this lane's W and V of slot k
     uint64_t vmask[K];
     bool kept[K];  // this lane's sample of slot k is in the frame (the bit of vmask[k])
@@ -590,6 +596,19 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
         kept[k] = valid;
     }
     wave_lds_sync();
+    order_test_lds<K, G>(Mv, W, tv, cx, cy, c, s, h, th, L, lane, wk, vk, vmask, kept, pofs);
+}
+
+// Ordering (Eq. (4)'s sort) and Eqs. (5)-(6) of one scanline whose samples
+// sit in registers (wk, vk, kept, pofs, vmask of slot k = offsets k*64 +
+// lane) and, by offset, in L.WVin / L.Oin.
+template <int K, int G>
+__device__ __forceinline__ void order_test_lds(uint8_t* __restrict__ Mv, int W, TileView tv, int cx, int cy,
+                                               float c, float s, int h, const Thresholds& th,
+                                               const WaveLds& L, int lane, const float (&wk)[K],
+                                               const float (&vk)[K], const uint64_t (&vmask)[K],
+                                               const bool (&kept)[K], const uint32_t (&pofs)[K]) {
+    constexpr int N = 64 * K;
     // descents W_e < W_{e-1} (both kept; NaN compares false): they split the
     // kept samples into maximal runs of non-decreasing W
     uint64_t dm[K];
@@ -753,6 +772,194 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
     wave_lds_sync();
 }
 
+// ---------------------------------------------------------------------------
+// Plain form (N = 1, nearest-pixel V, no routed tiles) of the scanlines of
+// at most 128 samples: samples, the one- and two-run orderings and the test
+// of Eq. (5) stay in registers; cross-lane traffic goes through DPP and
+// ds_bpermute, and only scanlines of three or more runs go through LDS.
+// ---------------------------------------------------------------------------
+// Wave-wide shift by one lane (DPP wave_shr:1 / wave_shl:1): lane i receives
+// v of lane i - 1 (up) or i + 1 (down); the lane that has no source lane
+// keeps `fill`.
+__device__ __forceinline__ float wave_up1(float v, float fill) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(v), 0x138, 0xF, 0xF,
+                                                      false));
+}
+__device__ __forceinline__ float wave_down1(float v, float fill) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(v), 0x130, 0xF, 0xF,
+                                                      false));
+}
+// v of lane `src & 63`
+__device__ __forceinline__ uint32_t lane_read(uint32_t v, int src) {
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((src & 63) << 2, (int)v);
+}
+__device__ __forceinline__ float lane_readf(float v, int src) {
+    return __uint_as_float(lane_read(__float_as_uint(v), src));
+}
+// slot-crossing reads of a K-slot array: element e = 64 * k + lane
+template <int K>
+__device__ __forceinline__ uint32_t elem_read(const uint32_t (&v)[K], int e) {
+    if constexpr (K == 1) {
+        return lane_read(v[0], e);
+    } else {
+        const uint32_t a = lane_read(v[0], e), b = lane_read(v[1], e);
+        return (e & 64) ? b : a;
+    }
+}
+
+// One stage of an ascending bitonic merge of the 64 K keys (element e =
+// 64 k + lane in key[k]): e and e ^ stride swap when out of order.
+template <int K>
+__device__ __forceinline__ void merge_stage(uint64_t (&key)[K], int stride, int lane) {
+    if (stride >= 64) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if ((k & (stride >> 6)) == 0) {
+                const int kp = k | (stride >> 6);
+                const uint64_t a = key[k], b = key[kp];
+                const bool sw = b < a;
+                key[k] = sw ? b : a;
+                key[kp] = sw ? a : b;
+            }
+        }
+    } else {
+        const bool lower = (lane & stride) == 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint64_t o = xchg64(key[k], stride, lane);
+            key[k] = ((o < key[k]) == lower) ? o : key[k];  // lower keeps the smaller, upper the larger
+        }
+    }
+}
+
+// Eq. (5) with one neighbour per side and Eq. (6) for sorted positions q =
+// 64 k + lane holding (W, V) of the sample whose pixel offset is po; W NaN
+// marks a position without a sample.
+template <int K>
+__device__ __forceinline__ void test_sorted(uint8_t* __restrict__ Mv, const float (&w)[K], const float (&v)[K],
+                                            const uint32_t (&po)[K], const Thresholds& th) {
+    const float NaN = __int_as_float(0x7fc00000);
+    auto lanef = [](float x, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l)); };
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int kp = k > 0 ? k - 1 : 0, kn = k + 1 < K ? k + 1 : k;
+        // neighbours across the slot boundary: lane 63 of slot k - 1, lane 0 of slot k + 1
+        const float wl = wave_up1(w[k], k > 0 ? lanef(w[kp], 63) : NaN);
+        const float vl = wave_up1(v[k], k > 0 ? lanef(v[kp], 63) : 0.0f);
+        const float wr = wave_down1(w[k], k + 1 < K ? lanef(w[kn], 0) : NaN);
+        const float vr = wave_down1(v[k], k + 1 < K ? lanef(v[kn], 0) : 0.0f);
+        const bool hit = ((fabsf(__fsub_rn(w[k], wl)) < th.zeta) & (__fsub_rn(vl, v[k]) > th.beta)) |
+                         ((fabsf(__fsub_rn(w[k], wr)) < th.zeta) & (__fsub_rn(vr, v[k]) > th.beta));
+        if (hit) Mv[po[k]] = 1;  // a NaN W (no sample here) never hits
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void scanline_plain(const float* __restrict__ D, int H, int W,
+                                               uint8_t* __restrict__ Mv, int cx, int cy, float c, float s,
+                                               float r, int h, int n, const Thresholds& th, const WaveLds& L,
+                                               int lane) {
+    constexpr int N = 64 * K;
+    const float NaN = __int_as_float(0x7fc00000);
+    float wk[K], vk[K];
+    uint64_t vmask[K];
+    bool kept[K];
+    uint32_t pofs[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int e = k * 64 + lane;
+        const float gf = (float)(e - h);
+        const int ix = (int)rintf(__fadd_rn((float)cx, __fmul_rn(c, gf)));
+        const int iy = (int)rintf(__fadd_rn((float)cy, __fmul_rn(s, gf)));
+        const bool valid = (e < n) & ((uint32_t)ix < (uint32_t)W) & ((uint32_t)iy < (uint32_t)H);
+        const uint32_t po = (uint32_t)iy * (uint32_t)W + (uint32_t)ix;  // H * W < 2^32
+        const float Vr = D[valid ? po : 0u];  // a dropped sample reads pixel 0 and is discarded
+        pofs[k] = po;
+        vk[k] = valid ? Vr : 0.0f;
+        wk[k] = valid ? __fsub_rn(gf, __fmul_rn(r, Vr)) : NaN;
+        vmask[k] = __ballot(valid);
+        kept[k] = valid;
+    }
+    // descents W_e < W_{e-1} (NaN compares false) split the kept samples,
+    // which form one contiguous range of offsets, into runs of
+    // non-decreasing W
+    uint64_t dm[K];
+    float wprev[K];
+    int nvalid = 0, e_lo = -1, ndesc = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const float fill =
+            k > 0 ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wk[k > 0 ? k - 1 : 0]), 63)) : NaN;
+        wprev[k] = wave_up1(wk[k], fill);
+        dm[k] = __ballot(wk[k] < wprev[k]);
+        ndesc += __popcll(dm[k]);
+        nvalid += __popcll(vmask[k]);
+        if (vmask[k] && e_lo < 0) e_lo = k * 64 + __ffsll((unsigned long long)vmask[k]) - 1;
+    }
+    if (nvalid == 0) return;
+    const int e_hi = e_lo + nvalid - 1;
+    if (ndesc == 0) {
+        // one run: the offsets are already in (W, g) order
+        uint32_t po[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) po[k] = pofs[k];
+        test_sorted<K>(Mv, wk, vk, po, th);
+        return;
+    }
+    if (ndesc == 1) {
+        // two runs A = [e_lo, j0) and B = [j0, e_hi]: keys (ord(W), e) of A in
+        // place, padded below by 0, and B reversed at the top, padded by ~0,
+        // form a bitonic sequence; a bitonic merge sorts it, and the kept
+        // samples then sit at positions e_lo .. e_hi
+        int j0 = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (dm[k]) j0 = k * 64 + __ffsll((unsigned long long)dm[k]) - 1;
+        const int lenB = e_hi - j0 + 1;
+        uint32_t wbits[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) wbits[k] = __float_as_uint(wk[k]);
+        uint64_t key[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int q = k * 64 + lane;
+            const int src = e_hi + N - lenB - q;  // B reversed: q in [N - lenB, N)
+            const float wB = __uint_as_float(elem_read<K>(wbits, src));
+            const uint64_t kA = ((uint64_t)f2ord(wk[k]) << 32) | (uint32_t)q;
+            const uint64_t kB = ((uint64_t)f2ord(wB) << 32) | (uint32_t)src;
+            key[k] = q < e_lo ? 0ull : (q < j0 ? kA : (q < N - lenB ? ~0ull : kB));
+        }
+#pragma unroll
+        for (int st = N / 2; st >= 1; st >>= 1) merge_stage<K>(key, st, lane);
+        uint32_t vbits[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) vbits[k] = __float_as_uint(vk[k]);
+        float ws[K], vs[K];
+        uint32_t po[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int q = k * 64 + lane;
+            const bool real = (q >= e_lo) & (q <= e_hi);
+            const int e = (int)(uint32_t)key[k];
+            ws[k] = real ? ord2f((uint32_t)(key[k] >> 32)) : NaN;
+            vs[k] = __uint_as_float(elem_read<K>(vbits, e));
+            po[k] = elem_read<K>(pofs, e);
+        }
+        test_sorted<K>(Mv, ws, vs, po, th);
+        return;
+    }
+    // three or more runs: through LDS
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int e = k * 64 + lane;
+        L.WVin[e] = make_float2(wk[k], vk[k]);
+        L.Oin[e] = f2ord(wk[k]);
+    }
+    wave_lds_sync();
+    TileView tv{nullptr, 0};
+    order_test_lds<K, 0>(Mv, W, tv, cx, cy, c, s, h, th, L, lane, wk, vk, vmask, kept, pofs);
+}
+
 template <int KMAX>
 constexpr int waves_per_block() { return KMAX >= 16 ? 2 : 4; }
 
@@ -803,7 +1010,12 @@ __device__ __forceinline__ void scan_item(const FrameDesc& f, int v, uint32_t pi
     }
     // the register class holds the view's longest window; a shorter one
     // (most merged windows) takes the smaller K
-    if constexpr (KMAX == 2) {
+    if constexpr (KMAX == 2 && G == 0) {
+        if (n <= 64)
+            scanline_plain<1>(f.D, H, W, Mv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, n, th, L, lane);
+        else
+            scanline_plain<2>(f.D, H, W, Mv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, n, th, L, lane);
+    } else if constexpr (KMAX == 2) {
         if (n <= 64)
             scanline<1, G>(f.D, H, W, Mv, tv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, n, th, L, lane);
         else
