@@ -206,6 +206,7 @@ LEARNED_PROFILE_CMD = ("rocprofv3 {mode} -d gpurun_out/{out} -o run -- python3 b
 BATCH_WORKLOAD = "c3 64 mixed frames seed 3000"
 C1_WORKLOAD = "c1 1280x960 x8 views seed 1002"
 C2_WORKLOAD = "c2 3840x2160 x15 views seed 2000"
+FUSED_KERNEL = "k_fused<16>"  # the fused pass at its tile height (rows per tile)
 C2_PROFILE_CMD = "rocprofv3 {mode} -d gpurun_out/{out} -o run -- python3 bench.py --c2-only --c2-steps 5"
 C2_KERNELS = ("k_edges<0>", "k_scanlines<4, 0>", "k_scanlines<8, 0>")
 QUALITY_WORKLOAD = "c1 1280x960 x8 views seeds 1000-1003"
@@ -280,9 +281,15 @@ def profiles_from(run_dir: str, workload: str) -> int:
     copy_kib = 256 * 1024
     f_read = max(cf.values()) / copy_kib if cf else None
     f_write = max(cw.values()) / copy_kib if cw else None
-    traffic = {"copy_probe": {"mib": 256, "fetch_kib": max(cf.values()) if cf else None,
+    traffic = {}
+    try:  # entries of runs not present here are kept
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
+            traffic = json.load(f)
+    except (OSError, ValueError):
+        pass
+    traffic["copy_probe"] = {"mib": 256, "fetch_kib": max(cf.values()) if cf else None,
                               "write_kib": max(cw.values()) if cw else None,
-                              "read_factor": f_read, "write_factor": f_write}}
+                              "read_factor": f_read, "write_factor": f_write}
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     runs = [("", PROFILE_CMD, lambda k: not k.startswith(LEARNED_KERNELS + QUALITY_KERNELS)),
             ("l", LEARNED_PROFILE_CMD, lambda k: k.startswith(LEARNED_KERNELS)),
@@ -305,7 +312,8 @@ def profiles_from(run_dir: str, workload: str) -> int:
             elif pre == "c":
                 wl = C2_WORKLOAD
             else:
-                wl = BATCH_WORKLOAD if ("batched" in k or "finish_frames" in k) else workload
+                wl = BATCH_WORKLOAD if any(x in k for x in ("batched", "finish_frames", "k_fused",
+                                                           "k_clear_masks")) else workload
             tag = wl.split(":")[0].replace(" ", "_").replace("x8_views", "v8")
             rd = fetch[k] * 1024 / (f_read or 1.0)
             wr = write[k] * 1024 / (f_write or 1.0)
@@ -419,18 +427,24 @@ def bench_c3(ctx, args):
     stages = ctx.occl_time_batched(max(3, min(args.steps, 20)))
     out = {"value": pv * args.steps / elapsed / 1e6, "ms_per_step": dt * 1e3, "pixel_views": pv,
            "alg_bytes": alg, "frames": frames, "masks": Ms, "launch_shape": shape, "stages_ms": stages}
-    scan_ms = stages["scanlines"]
-    roof = {"kernel": "k_scanlines_batched<2, 0>", "bound": "hbm",
-            "achieved": round(alg / (scan_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": round(alg / (scan_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-            "traffic": None, "avg_ms": round(scan_ms, 5), "launches_per_step": ctx_branches(),
-            "bytes_per_step": alg,
-            "note": "algorithmic bytes of the batch (D read once, every mask byte written once) over "
-                    "the batched scanline pass's time per batch (its launches re-run outside the "
-                    "graph, branch after branch, between HIP events)"}
-    t = traffic_for("k_scanlines_batched<2, 0>", BATCH_WORKLOAD)
+    if stages.get("form") == "fused":
+        kern, k_ms, launches = FUSED_KERNEL, stages["fused"], 1
+        note = ("algorithmic bytes of the batch (D read once, every mask byte written once) over the "
+                "fused pass's time per batch (Eqs. (1)-(6) in one launch; it and the mask fill before "
+                "it re-run outside the graph between HIP events)")
+    else:
+        kern, k_ms, launches = "k_scanlines_batched<2, 0>", stages["scanlines"], ctx_branches()
+        note = ("algorithmic bytes of the batch (D read once, every mask byte written once) over "
+                "the batched scanline pass's time per batch (its launches re-run outside the "
+                "graph, branch after branch, between HIP events)")
+    roof = {"kernel": kern, "bound": "hbm",
+            "achieved": round(alg / (k_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(alg / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+            "traffic": None, "avg_ms": round(k_ms, 5), "launches_per_step": launches,
+            "bytes_per_step": alg, "note": note}
+    t = traffic_for(kern, BATCH_WORKLOAD)
     if t is not None:
-        roof["traffic"] = t * roof["launches_per_step"]
+        roof["traffic"] = t * launches
     out["roofline"] = roof
     if not args.no_check:
         from concurrent.futures import ThreadPoolExecutor
@@ -444,11 +458,11 @@ def bench_c3(ctx, args):
             n_cand.append(nc)
         out["parity"] = {"frames": len(frames), "mismatches": bad}
         ops = sum(bitonic_ops(nc, f.scan_len) for nc, f in zip(n_cand, frames))
-        out["alu"] = {"kernel": "k_scanlines_batched<2, 0>", "ops_per_step": ops,
+        out["alu"] = {"kernel": kern, "ops_per_step": ops,
                       "count": "bitonic compare-exchanges of 2^ceil(log2 n) keys + 2 n neighbour tests "
                                "per scanline",
-                      "achieved_gops": round(ops / (scan_ms * 1e-3) / 1e9, 1), "peak_gops": ALU_PEAK_GOPS,
-                      "frac": round(ops / (scan_ms * 1e-3) / 1e9 / ALU_PEAK_GOPS, 4),
+                      "achieved_gops": round(ops / (k_ms * 1e-3) / 1e9, 1), "peak_gops": ALU_PEAK_GOPS,
+                      "frac": round(ops / (k_ms * 1e-3) / 1e9 / ALU_PEAK_GOPS, 4),
                       "scanlines": int(sum(int(np.sum(nc)) for nc in n_cand))}
     return out
 
@@ -861,7 +875,7 @@ def main() -> int:
         "hbm": {"alg_bytes_per_step": c3["alg_bytes"],
                 "path_gbps": round(c3["alg_bytes"] / (c3["ms_per_step"] * 1e-3) / 1e9, 1),
                 "path_frac": round(c3["alg_bytes"] / (c3["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)},
-        "stages_ms": {k: round(v, 5) for k, v in c3["stages_ms"].items()},
+        "stages_ms": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in c3["stages_ms"].items()},
     }
     for k in ("parity", "alu"):
         if k in c3:

@@ -377,13 +377,16 @@ occl_status occl_time_scanlines(occl_ctx* ctx, int32_t reps, double* ms_per_pass
 
 /* Stage timing of the most recent occl_detect_batched call: its kernels
  * re-enqueued `reps` times outside the graph, on the context's stream (the
- * graph's branches one after the other), with HIP events around the edge
- * stage (Eqs. (1)-(2), mask clear, per-frame prefix) and the scanline stage
- * (Eqs. (4)-(6)); ms (host double[2]) receives the mean milliseconds per
- * batch of each.  The masks are rewritten with the same values.  The
- * frames' D and M must still be valid.  Synchronises.  OCCL_ERR_STATE when
- * there is no such batch or its frame table has been reallocated since. */
-occl_status occl_time_batched(occl_ctx* ctx, int32_t reps, double* ms);
+ * graph's branches one after the other), with HIP events around each of its
+ * two stages; ms (host double[2]) receives the mean milliseconds per batch
+ * of each, form (host, may be NULL) which form the batch took:
+ *   0  two passes: [0] the edge stage (Eqs. (1)-(2), mask clear, per-frame
+ *      prefix), [1] the scanline stage (Eqs. (4)-(6));
+ *   1  fused: [0] the mask fill, [1] the fused pass (Eqs. (1)-(6)).
+ * The masks are rewritten with the same values.  The frames' D and M must
+ * still be valid.  Synchronises.  OCCL_ERR_STATE when there is no such
+ * batch or its frame table has been reallocated since. */
+occl_status occl_time_batched(occl_ctx* ctx, int32_t reps, double* ms, int32_t* form);
 
 const char* occl_status_string(occl_status s);
 const char* occl_last_error(const occl_ctx* ctx);

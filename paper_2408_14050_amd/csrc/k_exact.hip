@@ -1282,6 +1282,213 @@ __global__ __launch_bounds__(64 * batched_waves_per_block<KMAX>(), min_waves_per
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fused pass: Eqs. (1)-(6) of every view of one tile of kFusedRows x 256
+// pixels in one block, for frames whose views all have scanlines of at most
+// 128 samples (plain form).  The block loads the tile (one wavefront per
+// row, as the edge pass), keeps the candidates of every view in an LDS
+// queue, and its wavefronts run those scanlines right away, gathering D
+// from global memory.  No candidate list, list counter, prefix or second
+// launch is involved.  Hits are byte stores of 1 into masks that a fill
+// kernel has cleared before the pass (a scanline can write up to h pixels
+// outside its tile, so the tile cannot clear its own pixels).
+// Tiles are handed out by tickets: the flat tile list of the launch is cut
+// into kFusedParts contiguous parts, block b starts on part b % kFusedParts
+// (blocks are dealt to the 8 dies in turn, so each die mostly works on one
+// part and keeps that part's D in its L2) and moves on to the other parts
+// when its own is exhausted.
+// ---------------------------------------------------------------------------
+constexpr int kFusedParts = 8;
+
+template <int ROWS>
+struct FusedShared {
+    static constexpr int kQueue = ROWS * kEdgeCols;  // candidate entries per round (the tile's pixels)
+    uint32_t queue[kQueue];       // (v << 12) | (row << 8) | column of the tile
+    int cnt[OCCL_MAX_VIEWS];      // candidates per view in the tile
+    int qn;                       // entries in the queue
+    int take;                     // entries handed to wavefronts
+    int tile;                     // the block's current tile (-1: done)
+    int next;                     // the next one (fetched while the current one runs)
+};
+
+// Next tile for block `part0`'s thread 0: tickets of part p run from
+// pbeg[p] to pbeg[p + 1]; exhausted parts are skipped in turn.
+__device__ __forceinline__ int fused_ticket(unsigned* tickets, const int* pbeg, int& part, int part0) {
+    for (int k = 0; k < kFusedParts; ++k) {
+        const int p = (part0 + ((part - part0 + kFusedParts) % kFusedParts)) % kFusedParts;
+        const int t = pbeg[p] + (int)atomicAdd(&tickets[p * 32], 1u);
+        if (t < pbeg[p + 1]) return t;
+        part = (part + 1) % kFusedParts;
+        if (part == part0) break;
+    }
+    return -1;
+}
+
+// One tile (bx, by) of frame f.  Every thread of the block calls it.
+template <int ROWS>
+__device__ __forceinline__ void fused_tile(const FrameDesc& f, int bx, int by, int n_views, const ViewTable& vt,
+                                           const Thresholds& th, const WaveLds& L, FusedShared<ROWS>& S,
+                                           int wave, int lane) {
+    constexpr int kQ = FusedShared<ROWS>::kQueue;
+    const int H = f.H, W = f.W;
+    const int y = by * ROWS + wave;
+    const int x0 = bx * kEdgeCols + lane * 4;
+    const bool live = (y < H) && (x0 < W);
+    const EdgeIn in = edge_load(f, bx, by);
+    // Eq. (1) and the magnitude half of Eq. (2) (q >= q_min is sqrt_rn(q) > gamma)
+    float ex[4], ey[4];
+    unsigned strong = 0;
+    {
+        const bool next_row = (y + 1 < H);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float right = (j < 3) ? in.d0[j + 1] : in.dn;
+            ex[j] = (x0 + j + 1 < W) ? __fsub_rn(right, in.d0[j]) : 0.0f;
+            ey[j] = next_row ? __fsub_rn(in.d1[j], in.d0[j]) : 0.0f;
+            const float q = __fadd_rn(__fmul_rn(ex[j], ex[j]), __fmul_rn(ey[j], ey[j]));
+            strong |= (live && (x0 + j < W) && (q >= th.q_min)) ? (1u << j) : 0u;
+        }
+    }
+    auto cand = [&](int v, int j) {  // the direction half of Eq. (2)
+        const float dot = __fadd_rn(__fmul_rn(ex[j], vt.c[v]), __fmul_rn(ey[j], vt.s[v]));
+        return ((strong >> j) & 1u) && (dot > 0.0f);
+    };
+    const bool any = __ballot(strong != 0) != 0;
+    // candidates per view
+    if (any) {
+        for (int v = 0; v < n_views; ++v) {
+            int tot = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) tot += __popcll(__ballot(cand(v, j)));
+            if (lane == 0 && tot) atomicAdd(&S.cnt[v], tot);
+        }
+    }
+    __syncthreads();
+    int va = 0;
+    while (va < n_views) {
+        // the views of this round: as many as the queue holds (one view always fits)
+        int vb = va, acc = 0;
+        while (vb < n_views && acc + S.cnt[vb] <= kQ) acc += S.cnt[vb++];
+        if (any) {
+            for (int v = va; v < vb; ++v) {
+                uint64_t b[4];
+                int tot = 0, off = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    b[j] = __ballot(cand(v, j));
+                    tot += __popcll(b[j]);
+                    off += (int)lanes_below(b[j]);
+                }
+                if (tot == 0) continue;  // uniform
+                int base = 0;
+                if (lane == 0) base = atomicAdd(&S.qn, tot);
+                base = __builtin_amdgcn_readfirstlane(base);
+                uint32_t* dst = S.queue + base + off;
+                const uint32_t e0 = ((uint32_t)v << 12) | ((uint32_t)wave << 8) | (uint32_t)(lane * 4);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if ((b[j] >> lane) & 1ull) *dst++ = e0 + (uint32_t)j;
+            }
+        }
+        __syncthreads();
+        // wavefronts take entries as they finish their previous one
+        const int nq = S.qn;
+        for (;;) {
+            int i = 0;
+            if (lane == 0) i = atomicAdd(&S.take, 1);
+            i = __builtin_amdgcn_readfirstlane(i);
+            if (i >= nq) break;
+            const uint32_t ent = S.queue[i];
+            const int v = (int)(ent >> 12);
+            const int cy = by * ROWS + (int)((ent >> 8) & 15u);
+            const int cx = bx * kEdgeCols + (int)(ent & 255u);
+            const int h = f.h[v];
+            const int n = 2 * h + 1;
+            uint8_t* Mv = f.M + (size_t)v * H * W;
+            if (n <= 64)
+                scanline_plain<1>(f.D, H, W, Mv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, n, th, L, lane);
+            else
+                scanline_plain<2>(f.D, H, W, Mv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, n, th, L, lane);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            S.qn = 0;
+            S.take = 0;
+        }
+        va = vb;
+        if (va < n_views) __syncthreads();
+    }
+}
+
+// All frames of the launch (one for a single frame): a persistent grid
+// walks the tiles by tickets.  tickets: kFusedParts counters 128 bytes
+// apart, zero at launch (the mask fill kernel clears them).
+template <int ROWS>
+__global__ __launch_bounds__(64 * ROWS, 8) void k_fused(const FrameDesc* __restrict__ table, int n_frames,
+                                                        int total_tiles, int n_views, ViewTable vt, Thresholds th,
+                                                        unsigned* tickets) {
+    __shared__ FusedShared<ROWS> S;
+    __shared__ int begin[kMaxBatch + 1];
+    __shared__ int pbeg[kFusedParts + 1];
+    __shared__ float2 lds[ROWS][2][128];
+    __shared__ uint32_t okeys[ROWS][128];
+    __shared__ int runs[ROWS][kMaxRunsCap + 1];
+    for (int i = threadIdx.x; i < n_frames; i += blockDim.x) begin[i] = table[i].block_begin;
+    if (threadIdx.x == 0) begin[n_frames] = total_tiles;
+    if (threadIdx.x <= kFusedParts) pbeg[threadIdx.x] = (int)((long long)total_tiles * threadIdx.x / kFusedParts);
+    for (int v = threadIdx.x; v < n_views; v += blockDim.x) S.cnt[v] = 0;
+    const int part0 = (int)(blockIdx.x % kFusedParts);
+    int part = part0;  // thread 0's current part
+    if (threadIdx.x == 0) {
+        S.qn = 0;
+        S.take = 0;
+        S.tile = fused_ticket(tickets, pbeg, part, part0);
+    }
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const WaveLds L{lds[wave][0], okeys[wave], lds[wave][1], runs[wave]};
+    int fi = 0;
+    for (;;) {
+        const int t = S.tile;
+        if (t < 0) break;
+        if (threadIdx.x == 0) S.next = fused_ticket(tickets, pbeg, part, part0);
+        int a = 0, b = n_frames - 1;  // frame of tile t: last with begin <= t
+        while (a < b) {
+            const int mid = (a + b + 1) >> 1;
+            if (begin[mid] <= t) a = mid; else b = mid - 1;
+        }
+        fi = a;
+        const FrameDesc& f = table[fi];
+        const int local = t - begin[fi];
+        fused_tile<ROWS>(f, local % f.gx, local / f.gx, n_views, vt, th, L, S, wave, lane);
+        if (threadIdx.x < n_views) S.cnt[threadIdx.x] = 0;
+        if (threadIdx.x == 0) S.tile = S.next;
+        __syncthreads();
+    }
+}
+
+// Clears the masks of the launch's frames (16-byte stores where aligned):
+// block (x, fi) clears bytes [x * kClearChunkBytes, (x + 1) * kClearChunkBytes) of
+// frame fi's masks; block (0, 0) also clears the fused pass's tickets.
+__global__ __launch_bounds__(256) void k_clear_masks(const FrameDesc* __restrict__ table, int n_views,
+                                                     unsigned* tickets) {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < kFusedParts) tickets[threadIdx.x * 32] = 0u;
+    const FrameDesc& f = table[blockIdx.y];
+    const long long bytes = (long long)f.H * f.W * n_views;
+    const long long o0 = (long long)blockIdx.x * kClearChunkBytes;
+    if (o0 >= bytes) return;
+    const long long o1 = o0 + kClearChunkBytes < bytes ? o0 + kClearChunkBytes : bytes;
+    uint8_t* M = f.M;
+    if ((((uintptr_t)M) & 15) == 0) {
+        long long o = o0 + (long long)threadIdx.x * 16;
+        for (; o + 16 <= o1; o += 256 * 16) *reinterpret_cast<uint4*>(M + o) = make_uint4(0u, 0u, 0u, 0u);
+        for (; o < o1; ++o) M[o] = 0;  // the frame's last partial vector: one thread
+    } else {
+        for (long long o = o0 + threadIdx.x; o < o1; o += 256) M[o] = 0;
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1433,6 +1640,36 @@ hipError_t launch_scanlines(hipStream_t st, const FrameDesc& f, int n_views, con
 }
 
 // Batched frames are never routed (no tile states) and never thinned.
+int fused_blocks_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fused<kFusedTileRows>, 64 * kFusedTileRows, 0) !=
+            hipSuccess ||
+        nb < 1)
+        nb = 1;
+    return nb;
+}
+
+hipError_t launch_fused_stage(hipStream_t st, const FrameDesc* table, int n_frames, int total_tiles, int n_views,
+                              const ViewTable& vt, const Thresholds& th, unsigned* tickets, int n_blocks,
+                              int clear_blocks, int stage) {
+    if (stage == 0)
+        hipLaunchKernelGGL(k_clear_masks, dim3(clear_blocks, n_frames), dim3(256), 0, st, table, n_views, tickets);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fused<kFusedTileRows>), dim3(n_blocks), dim3(64 * kFusedTileRows), 0,
+                           st, table, n_frames, total_tiles, n_views, vt, th, tickets);
+    return hipGetLastError();
+}
+
+hipError_t launch_fused(hipStream_t st, const FrameDesc* table, int n_frames, int total_tiles, int n_views,
+                        const ViewTable& vt, const Thresholds& th, unsigned* tickets, int n_blocks,
+                        int clear_blocks) {
+    hipError_t e = launch_fused_stage(st, table, n_frames, total_tiles, n_views, vt, th, tickets, n_blocks,
+                                      clear_blocks, 0);
+    if (e == hipSuccess)
+        e = launch_fused_stage(st, table, n_frames, total_tiles, n_views, vt, th, tickets, n_blocks, clear_blocks, 1);
+    return e;
+}
+
 hipError_t launch_scanlines_batched(hipStream_t st, const FrameDesc* table, int n_frames,
                                     int n_views, const ViewTable& vt, const Thresholds& th,
                                     int cls, int n_blocks) {

@@ -461,7 +461,8 @@ occl_status occl_ctx::enqueue_frame(const float* D, int H, int W, int n_views, c
                                     const uint8_t* tnear, const FrameWorkspace* ws) {
     int maxcls = 0;
     for (int v = 0; v < n_views; ++v) maxcls = std::max(maxcls, scan_class(Ls[v] / 2, th.thin));
-    const TuneConfig tc = cfg ? *cfg : config_for(tune_key(false, (size_t)H * W, n_views, maxcls));
+    TuneConfig tc = cfg ? *cfg : config_for(tune_key(false, (size_t)H * W, n_views, maxcls));
+    if (tc.edge_rows < 1) tc.edge_rows = tune_default.edge_rows;  // 0 (the fused form) is for batches
     FrameDesc f;
     describe_frame(&f, D, M, H, W, n_views, Ls, tc.edge_rows, th.thin);
     if (ws) {

@@ -26,6 +26,7 @@ using namespace occl;
 namespace {
 
 struct BatchSig {
+    int fused;  // 1: clear + fused pass (k_fused), 0: edge and scanline passes
     const void* table;
     int n_frames, total_blocks, n_views, edge_rows, edge_grid, scan_grid;
     int n_branches;
@@ -53,7 +54,16 @@ occl_status occl_ctx::enqueue_batch(int n_frames, const occl_frame* frames, int 
         px += (size_t)frames[f].H * frames[f].W;
         for (int v = 0; v < n_views; ++v) maxcls = std::max(maxcls, scan_class(Ls_all[f * n_views + v] / 2));
     }
-    const TuneConfig tc = cfg ? *cfg : config_for(tune_key(true, px, n_views, maxcls));
+    const uint64_t bucket = tune_key(true, px, n_views, maxcls);
+    TuneConfig tc = cfg ? *cfg : config_for(bucket);
+    // edge_rows 0 selects the fused pass where the batch allows it; it is
+    // also the default of a bucket the autotuner has not measured (64 mixed
+    // frames: 1.40 ms against 1.58-1.61 ms for the two passes)
+    if (!cfg && tuned.find(bucket) == tuned.end()) tc.edge_rows = 0;
+    if (tc.edge_rows == 0) {
+        if (fusable(n_views, maxcls, th)) return enqueue_batch_fused(n_frames, frames, n_views, Ls_all, vt, th);
+        tc.edge_rows = tune_default.edge_rows;
+    }
     hipError_t e;
     if (!table_host) {
         e = hipHostMalloc((void**)&table_host, kMaxBatch * sizeof(FrameDesc), hipHostMallocDefault);
@@ -229,6 +239,7 @@ occl_status occl_ctx::enqueue_batch(int n_frames, const occl_frame* frames, int 
     ++graph_launches;
     LastBatch& lb = last_batch;
     lb.valid = true;
+    lb.fused = false;
     lb.table = (const FrameDesc*)table;
     lb.n_branches = nb;
     lb.n_views = n_views;
@@ -245,12 +256,134 @@ occl_status occl_ctx::enqueue_batch(int n_frames, const occl_frame* frames, int 
     return OCCL_OK;
 }
 
+bool occl_ctx::fusable(int n_views, int maxcls, const Thresholds& th) const {
+    return maxcls == 0 && n_views >= 1 && n_views <= kFusedMaxViews && th.ns == 1 && !th.bilinear && !th.thin;
+}
+
+// The fused form of a batch: one fill kernel clears every mask (and the
+// tickets), then one persistent launch runs Eqs. (1)-(6) tile by tile.
+occl_status occl_ctx::enqueue_batch_fused(int n_frames, const occl_frame* frames, int n_views, const int* Ls_all,
+                                          const ViewTable& vt, const Thresholds& th) {
+    hipError_t e;
+    if (!table_host) {
+        e = hipHostMalloc((void**)&table_host, kMaxBatch * sizeof(FrameDesc), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            table_host = nullptr;
+            return hip_fail(e, "hipHostMalloc(frame table)");
+        }
+        e = hipEventCreateWithFlags(&table_event, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    } else {
+        e = hipEventSynchronize(table_event);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize(table)");
+    }
+    int total_tiles = 0;
+    long long chunks = 0;
+    for (int f = 0; f < n_frames; ++f) {
+        FrameDesc& d = table_host[f];
+        describe_frame(&d, frames[f].D, frames[f].M, frames[f].H, frames[f].W, n_views,
+                       Ls_all + (size_t)f * n_views, kFusedTileRows);
+        d.block_begin = total_tiles;
+        d.lists = nullptr;
+        d.counts = nullptr;
+        d.prefix = nullptr;
+        total_tiles += d.gx * d.gy;
+        chunks = std::max<long long>(chunks, ((long long)frames[f].H * frames[f].W * n_views + kClearChunkBytes - 1) /
+                                                 kClearChunkBytes);
+    }
+    void *table, *tickets;
+    occl_status s = ensure("btable", (size_t)n_frames * sizeof(FrameDesc), &table);
+    if (s == OCCL_OK) s = ensure("ftickets", kFusedTickets * sizeof(uint32_t), &tickets);
+    if (s != OCCL_OK) return s;
+    e = hipMemcpyAsync(table, table_host, (size_t)n_frames * sizeof(FrameDesc), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipEventRecord(table_event, stream);
+    if (e != hipSuccess) return hip_fail(e, "frame table upload");
+    const int grid = n_cu * fused_blocks_per_cu();
+    const int clear_grid = (int)chunks;  // chunks of the largest frame (grid y: frames)
+    BatchSig sg;
+    std::memset(&sg, 0, sizeof(sg));
+    sg.fused = 1;
+    sg.table = table;
+    sg.n_frames = n_frames;
+    sg.total_blocks = total_tiles;
+    sg.n_views = n_views;
+    sg.scan_grid = grid;
+    sg.edge_grid = clear_grid;
+    sg.th = th;
+    sg.vt = vt;
+    const std::vector<uint8_t> key = sig_bytes(sg);
+    hipGraphExec_t exec = nullptr;
+    for (size_t i = 0; i < graphs.size(); ++i) {
+        if (graphs[i].sig == key) {
+            exec = graphs[i].exec;
+            std::rotate(graphs.begin(), graphs.begin() + i, graphs.begin() + i + 1);
+            break;
+        }
+    }
+    if (!exec) {
+        if (!cap_stream) {
+            e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
+            if (e != hipSuccess) {
+                cap_stream = nullptr;
+                return hip_fail(e, "hipStreamCreate(capture)");
+            }
+        }
+        e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        const hipError_t le = launch_fused(cap_stream, (const FrameDesc*)table, n_frames, total_tiles, n_views, vt,
+                                           th, (unsigned*)tickets, grid, clear_grid);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(cap_stream, &graph);
+        if (le != hipSuccess || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return hip_fail(le != hipSuccess ? le : e, "batch capture");
+        }
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        GraphEntry g;
+        g.sig = key;
+        g.graph = graph;
+        g.exec = exec;
+        graphs.insert(graphs.begin(), std::move(g));
+        while (graphs.size() > 4) {
+            (void)hipGraphExecDestroy(graphs.back().exec);
+            (void)hipGraphDestroy(graphs.back().graph);
+            graphs.pop_back();
+        }
+        ++graph_builds;
+    }
+    hipEvent_t ev = prof_begin(OCCL_STAGE_BATCHED);
+    e = hipGraphLaunch(exec, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    prof_end(OCCL_STAGE_BATCHED, ev);
+    ++graph_launches;
+    LastBatch& lb = last_batch;
+    lb.valid = true;
+    lb.fused = true;
+    lb.table = (const FrameDesc*)table;
+    lb.tickets = (unsigned*)tickets;
+    lb.n_branches = 1;
+    lb.cut[0] = 0;
+    lb.cut[1] = n_frames;
+    lb.bstart[0] = 0;
+    lb.bstart[1] = total_tiles;
+    lb.n_views = n_views;
+    lb.edge_grid = clear_grid;
+    lb.scan_grid = grid;
+    lb.vt = vt;
+    lb.th = th;
+    return OCCL_OK;
+}
+
 // Stage timing of the most recent batch: its kernels re-enqueued eagerly on
 // the context's stream (the graph's branches one after the other), `reps`
 // times, with HIP events around the edge stage (edge pass + per-frame
 // prefix) and the scanline stage of every repetition.  Re-running the
 // sequence rewrites the same masks.
-extern "C" occl_status occl_time_batched(occl_ctx* ctx, int32_t reps, double* ms) {
+extern "C" occl_status occl_time_batched(occl_ctx* ctx, int32_t reps, double* ms, int32_t* form) {
     if (!ctx || !ms || reps < 1) return OCCL_ERR_INVALID_ARG;
     const occl_ctx::LastBatch& lb = ctx->last_batch;
     auto tb = ctx->bufs.find("btable");
@@ -266,7 +399,25 @@ extern "C" occl_status occl_time_batched(occl_ctx* ctx, int32_t reps, double* ms
         }
     double acc[2] = {0.0, 0.0};
     hipError_t e = hipSuccess;
-    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+    for (int r = 0; r < reps && e == hipSuccess && lb.fused; ++r) {
+        // fused form: the mask fill, then the fused pass
+        e = hipEventRecord(ev[0], ctx->stream);
+        if (e == hipSuccess)
+            e = launch_fused_stage(ctx->stream, lb.table, lb.cut[1], lb.bstart[1], lb.n_views, lb.vt, lb.th,
+                                   lb.tickets, lb.scan_grid, lb.edge_grid, 0);
+        if (e == hipSuccess) e = hipEventRecord(ev[1], ctx->stream);
+        if (e == hipSuccess)
+            e = launch_fused_stage(ctx->stream, lb.table, lb.cut[1], lb.bstart[1], lb.n_views, lb.vt, lb.th,
+                                   lb.tickets, lb.scan_grid, lb.edge_grid, 1);
+        if (e == hipSuccess) e = hipEventRecord(ev[2], ctx->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[2]);
+        float t0 = 0.0f, t1 = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t0, ev[0], ev[1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t1, ev[1], ev[2]);
+        acc[0] += t0;
+        acc[1] += t1;
+    }
+    for (int r = 0; r < reps && e == hipSuccess && !lb.fused; ++r) {
         e = hipEventRecord(ev[0], ctx->stream);
         for (int b = 0; b < lb.n_branches && e == hipSuccess; ++b) {
             const int nf = lb.cut[b + 1] - lb.cut[b], blocks = lb.bstart[b + 1] - lb.bstart[b];
@@ -291,6 +442,7 @@ extern "C" occl_status occl_time_batched(occl_ctx* ctx, int32_t reps, double* ms
     if (e != hipSuccess) return ctx->hip_fail(e, "time_batched");
     ms[0] = acc[0] / reps;
     ms[1] = acc[1] / reps;
+    if (form) *form = lb.fused ? 1 : 0;
     return OCCL_OK;
 }
 
@@ -400,9 +552,18 @@ occl_status time_config(occl_ctx* ctx, F&& enqueue, int reps, float* ms) {
 }
 
 template <class F>
-occl_status search(occl_ctx* ctx, F&& enqueue_with, int reps, TuneConfig* best, float* best_ms) {
+occl_status search(occl_ctx* ctx, F&& enqueue_with, int reps, TuneConfig* best, float* best_ms,
+                   bool try_fused = false) {
     *best = ctx->tune_default;
     *best_ms = INFINITY;
+    if (try_fused) {
+        const TuneConfig c{0, ctx->tune_default.scan_blocks_per_cu};
+        float ms;
+        occl_status s = time_config(ctx, [&] { return enqueue_with(c); }, reps, &ms);
+        if (s != OCCL_OK) return s;
+        *best_ms = ms;
+        *best = c;
+    }
     for (int er : kEdgeRowsCand) {
         TuneConfig c{er, best->scan_blocks_per_cu};
         float ms;
@@ -477,15 +638,15 @@ extern "C" occl_status occl_autotune_batched(occl_ctx* ctx, int32_t n_frames, co
     const Thresholds th = make_thresholds(params);
     TuneConfig best;
     float best_ms;
-    s = search(ctx, [&](const TuneConfig& c) { return run_batch(ctx, live, Ls, n_views, vt, th, &c); },
-               reps > 0 ? reps : 5, &best, &best_ms);
-    if (s != OCCL_OK) return s;
     size_t px = 0;
     int maxcls = 0;
     for (size_t f = 0; f < live.size(); ++f) {
         px += (size_t)live[f].H * live[f].W;
         for (int v = 0; v < n_views; ++v) maxcls = std::max(maxcls, scan_class(Ls[f * n_views + v] / 2));
     }
+    s = search(ctx, [&](const TuneConfig& c) { return run_batch(ctx, live, Ls, n_views, vt, th, &c); },
+               reps > 0 ? reps : 5, &best, &best_ms, ctx->fusable(n_views, maxcls, th));
+    if (s != OCCL_OK) return s;
     ctx->tuned[tune_key(true, px, n_views, maxcls)] = best;
     if (out) {
         out->edge_rows = best.edge_rows;
@@ -517,7 +678,7 @@ extern "C" occl_status occl_tune_load(occl_ctx* ctx, const char* path) {
         if (line[0] == '#' || line[0] == '\n') continue;
         unsigned long long k;
         int er, bpc;
-        if (std::sscanf(line, "%llu %d %d", &k, &er, &bpc) != 3 || er < 1 || er > kMaxEdgeRows ||
+        if (std::sscanf(line, "%llu %d %d", &k, &er, &bpc) != 3 || er < 0 || er > kMaxEdgeRows ||
             (er & (er - 1)) != 0 || bpc < 1 || bpc > 64) {
             std::fclose(fp);
             return ctx->fail(OCCL_ERR_INVALID_ARG, "malformed tune file");

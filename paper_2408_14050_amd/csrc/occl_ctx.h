@@ -67,7 +67,9 @@ struct occl_ctx {
     // the most recent batch's launch sequence (occl_time_batched re-runs it)
     struct LastBatch {
         bool valid = false;
+        bool fused = false;                      // the batch took the fused pass
         const occl::FrameDesc* table = nullptr;  // device frame table
+        unsigned* tickets = nullptr;             // the fused pass's tile tickets
         int n_branches = 0, n_views = 0, edge_rows = 0, edge_grid = 0, scan_grid = 0;
         int cut[occl::kMaxBatchBranches + 1] = {};
         int bstart[occl::kMaxBatchBranches + 1] = {};
@@ -132,6 +134,11 @@ struct occl_ctx {
     occl_status enqueue_batch(int n_frames, const occl_frame* frames, int n_views, const int* Ls_all,
                               const occl::ViewTable& vt, const occl::Thresholds& th,
                               const occl::TuneConfig* cfg);
+    // the fused pass takes batches whose views all have scanlines of at most
+    // 128 samples, in the plain form (N = 1, nearest-pixel V)
+    bool fusable(int n_views, int maxcls, const occl::Thresholds& th) const;
+    occl_status enqueue_batch_fused(int n_frames, const occl_frame* frames, int n_views, const int* Ls_all,
+                                    const occl::ViewTable& vt, const occl::Thresholds& th);
 
     bool cnn_ready() const { return cnn_loaded; }
     occl_status enqueue_frame_cnn(const float* D, int H, int W, int n_views, const int* Ls,

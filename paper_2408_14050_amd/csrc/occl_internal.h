@@ -166,6 +166,30 @@ hipError_t launch_scanlines_batched(hipStream_t st, const FrameDesc* table, int 
                                     int n_views, const ViewTable& vt, const Thresholds& th,
                                     int cls, int n_blocks);
 
+// Fused pass (k_fused, after k_clear_masks): every view of every frame in
+// one persistent launch, for frames whose views all have scanlines of at
+// most 128 samples, the plain form (N = 1, nearest-pixel V, no routed tiles,
+// no thinning) and at most kFusedMaxViews views.  Frames are described with
+// tiles of kFusedTileRows rows x kEdgeCols columns (describe_frame with
+// edge_rows = kFusedTileRows; block_begin = first flat tile).  tickets:
+// kFusedParts counters 128 bytes apart (cleared by the launch itself).
+#ifndef OCCL_FUSED_ROWS
+#define OCCL_FUSED_ROWS 16
+#endif
+constexpr int kFusedTileRows = OCCL_FUSED_ROWS;  // rows (wavefronts) per tile, at most 16
+static_assert(kFusedTileRows >= 1 && kFusedTileRows <= 16, "fused tile rows");
+constexpr int kClearChunkBytes = 65536;  // bytes of mask per block of the mask fill
+constexpr int kFusedTickets = 8 * 32;  // uint32 of the tickets buffer
+constexpr int kFusedMaxViews = 64;
+int fused_blocks_per_cu();
+// one kernel of the fused form: stage 0 the mask fill, stage 1 the fused pass
+hipError_t launch_fused_stage(hipStream_t st, const FrameDesc* table, int n_frames, int total_tiles, int n_views,
+                              const ViewTable& vt, const Thresholds& th, unsigned* tickets, int n_blocks,
+                              int clear_blocks, int stage);
+hipError_t launch_fused(hipStream_t st, const FrameDesc* table, int n_frames, int total_tiles, int n_views,
+                        const ViewTable& vt, const Thresholds& th, unsigned* tickets, int n_blocks,
+                        int clear_blocks);
+
 // Smallest fp32 q >= 0 whose correctly rounded square root exceeds gamma
 // (-inf when gamma < 0: every magnitude passes).  Host only.
 float edge_q_min(float gamma);

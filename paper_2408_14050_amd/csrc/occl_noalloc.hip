@@ -93,7 +93,8 @@ extern "C" occl_status occl_detect_noalloc(occl_ctx* ctx, const float* D, int32_
     // it needs
     int maxcls = 0;
     for (int v = 0; v < n_views; ++v) maxcls = std::max(maxcls, scan_class(Ls[v] / 2, th.thin));
-    const TuneConfig tc = ctx->config_for(tune_key(false, (size_t)H * W, n_views, maxcls));
+    TuneConfig tc = ctx->config_for(tune_key(false, (size_t)H * W, n_views, maxcls));
+    if (tc.edge_rows < 1) tc.edge_rows = ctx->tune_default.edge_rows;
     FrameDesc f;
     describe_frame(&f, D, M, H, W, n_views, Ls, tc.edge_rows, th.thin);
     const size_t need = kOffLists + list_entries(f, n_views) * sizeof(uint32_t);

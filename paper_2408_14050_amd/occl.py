@@ -97,7 +97,7 @@ _SIGS = {
     "occl_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "occl_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "occl_time_scanlines": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
-    "occl_time_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
+    "occl_time_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "occl_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
                                 C.POINTER(C.c_double), C.POINTER(C.c_float), C.POINTER(occl_params),
                                 C.c_void_p, C.c_int32, C.POINTER(occl_tune)]),
@@ -446,12 +446,16 @@ class Context:
         return ms.value
 
     def occl_time_batched(self, reps: int = 20):
-        """Mean ms per batch of the edge stage and the scanline stage of the
-        last occl_detect_batched, re-run `reps` times outside the graph."""
+        """Mean ms per batch of the two stages of the last
+        occl_detect_batched (edge and scanline passes, or mask fill and
+        fused pass), re-run `reps` times outside the graph."""
         ms = np.zeros(2, np.float64)
-        self._check(lib().occl_time_batched(self.h, int(reps), ms.ctypes.data_as(C.POINTER(C.c_double))),
-                    "occl_time_batched")
-        return {"edges": float(ms[0]), "scanlines": float(ms[1])}
+        form = C.c_int32()
+        self._check(lib().occl_time_batched(self.h, int(reps), ms.ctypes.data_as(C.POINTER(C.c_double)),
+                                            C.byref(form)), "occl_time_batched")
+        if form.value == 1:
+            return {"form": "fused", "clear": float(ms[0]), "fused": float(ms[1])}
+        return {"form": "two-pass", "edges": float(ms[0]), "scanlines": float(ms[1])}
 
     def occl_detect_routed(self, D, angles, ratios, prm: occl_params, logits, M=None,
                            tile_state=None):
