@@ -38,6 +38,8 @@ from paper_2408_14050_amd import scenes  # noqa: E402
 CROP = 256
 TRAIN_SEED0 = 400000
 EVAL_SEED0 = 4100
+CALIB_SEED0 = 4200      # calibration frames: disjoint from training and evaluation seeds
+LAST_LAYER_PARAMS = 3 * 3 * 32 + 1  # the final 32 -> 1 convolution's weights and bias (end of theta)
 DEFAULT_WEIGHTS = os.path.join(HERE, "weights", "tile_cnn_c1.npz")
 
 
@@ -187,6 +189,73 @@ def evaluate(ctx, n_frames, bands, W=1920, H=1080):
     return out
 
 
+def routed_iou(ctx, frames, band, scale=1.0):
+    """Pooled IoU (Eq. 7 counts) of routed against exact masks, the logits
+    scaled by `scale` on the way (a trial of the calibration; the shipped
+    weights carry the scale in their last layer instead), and the share of
+    tiles that fall back."""
+    import torch
+    from paper_2408_14050_amd import occl
+    tp = fp = fn = ex = nt = 0
+    for D, M, Z, Ls, angles, ratios in frames:
+        st = torch.empty(Z.shape, dtype=torch.uint8, device="cuda")
+        prm = occl.params(scan_len_per_view=Ls, cnn_lo=band[0], cnn_hi=band[1])
+        Mr = ctx.occl_detect_routed(D, angles, ratios, prm, Z * scale if scale != 1.0 else Z, tile_state=st)
+        c = ctx.occl_confusion(Mr, M)
+        tp, fp, fn = tp + c["tp"], fp + c["fp"], fn + c["fn"]
+        ex += int((st == 2).sum().item())
+        nt += st.numel()
+    return tp / max(1, tp + fp + fn), ex / max(1, nt)
+
+
+def calibrate(ctx, n_frames, band=(0.05, 0.95), target=0.992, W=1920, H=1080):
+    """Temperature calibration of the proposal: the largest scale t in
+    (0, 1] of the logits for which the routed masks of n_frames calibration
+    frames (seeds CALIB_SEED0...) reach `target` IoU against the exact masks
+    at the configured band.  t is folded into the last layer (its weights
+    and bias times t), so inference is unchanged; the result is checked
+    again with the scaled weights.  Returns the table of trials."""
+    import torch
+    from paper_2408_14050_amd import occl
+    angles, ratios = scenes.views_3x3()
+
+    def frames_now():
+        out = []
+        for k in range(n_frames):
+            sc = scenes.make_c1_like(CALIB_SEED0 + k, W=W, H=H)
+            D = torch.from_numpy(sc.D).cuda()
+            M = ctx.occl_detect(D, angles, ratios, occl.params(scan_len_per_view=sc.scan_len))
+            Z = ctx.occl_cnn_propose(D, angles, ratios, sc.scan_len)
+            out.append((D, M, Z, sc.scan_len, angles, ratios))
+        return out
+
+    frames = frames_now()
+    trials = []
+    t = 1.0
+    chosen = None
+    while t > 0.2:
+        iou, share = routed_iou(ctx, frames, band, t)
+        trials.append({"scale": round(t, 4), "iou": round(iou, 5), "exact_tile_share": round(share, 5)})
+        if iou >= target and chosen is None:
+            chosen = t
+            break
+        t -= 0.02
+    if chosen is None:
+        raise RuntimeError(f"no scale reaches IoU {target}: {trials}")
+    th, m, v, step = ctx.occl_cnn_get_state()
+    for scale in (chosen, chosen - 0.02, chosen - 0.04):
+        th2 = th.copy()
+        th2[-LAST_LAYER_PARAMS:] *= np.float32(scale)
+        ctx.occl_cnn_set_state(th2, m, v, step)
+        iou, share = routed_iou(ctx, frames_now(), band)
+        trials.append({"scale": round(scale, 4), "folded": True, "iou": round(iou, 5),
+                       "exact_tile_share": round(share, 5)})
+        if iou >= target:
+            return {"scale": round(scale, 4), "band": list(band), "target_iou": target,
+                    "calibration_seeds": [CALIB_SEED0, CALIB_SEED0 + n_frames - 1], "trials": trials}
+    raise RuntimeError(f"folded scales miss IoU {target}: {trials}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--frames", type=int, default=2500)
@@ -201,13 +270,23 @@ def main():
     ap.add_argument("--eval", type=int, default=16, help="held-out 1920x1080 frames (0: skip)")
     ap.add_argument("--eval-only", action="store_true")
     ap.add_argument("--save-optimizer", action="store_true", help="also save Adam moments")
+    ap.add_argument("--calibrate", type=int, default=0, metavar="N",
+                    help="temperature-calibrate the saved weights on N frames for IoU 0.992 at [0.05, 0.95] "
+                         "(a margin over the 0.99 bar) and save them again")
     args = ap.parse_args()
-    if args.eval_only:
+    if args.eval_only or args.calibrate:
         from paper_2408_14050_amd import occl
         ctx = occl.Context(0)
-        load_state(ctx, args.out)
+        meta = load_state(ctx, args.out)
     else:
         ctx = train(args)
+    if args.calibrate:
+        if "calibration" in meta:
+            raise SystemExit(f"{args.out} is calibrated already: {meta['calibration']}")
+        cal = calibrate(ctx, args.calibrate)
+        meta["calibration"] = cal
+        print("calibration", json.dumps(cal), flush=True)
+        save_state(ctx, args.out, meta)
     if args.eval:
         bands = [(0.05, 0.95), (0.02, 0.98), (0.01, 0.99), (0.005, 0.995), (0.002, 0.998)]
         res = evaluate(ctx, args.eval, bands)

@@ -422,24 +422,52 @@ def test_routed_validates(gctx, torch):
         gctx._check(st, "routed without logits")
 
 
-def test_committed_weights_quality(gctx, torch):
-    """The shipped proposal (trained by train_tile_cnn on 20k crops) on a
-    held-out 1920x1080 frame: IoU of the routed masks against the exact
-    masks (Eq. 7 counts) and the share of tiles that fall back."""
+def test_committed_weights_quality(gctx, torch, record_property):
+    """The shipped proposal (trained by train_tile_cnn on 20k crops, its
+    logits temperature-calibrated on frames 4200..4215) on held-out
+    1920x1080 frames at the configured band [0.05, 0.95]: IoU of the
+    routed masks against the exact masks (Eq. 7 counts) must reach 0.99.
+    The speed of CNN + fallback against the exact path is measured and
+    recorded; the target (faster than exact) is not met on this GPU: the
+    exact path already skips the tiles the network is confident about."""
+    import time
     from paper_2408_14050_amd import occl
     from paper_2408_14050_amd.train_tile_cnn import load_state
     meta = load_state(gctx)
     assert meta["frames"] * meta["crops_per_frame"] >= 20000
+    assert "calibration" in meta and meta["calibration"]["band"] == [0.05, 0.95]
     angles, ratios = scenes.views_3x3()
-    sc = scenes.make_c1_like(4115, W=1920, H=1080)
-    D = to_dev(torch, sc.D)
-    M = gctx.occl_detect(D, angles, ratios, occl.params(scan_len_per_view=sc.scan_len))
-    prm = occl.params(scan_len_per_view=sc.scan_len, flags=occl.FLAG_USE_CNN | occl.FLAG_SYNC,
-                      cnn_lo=0.02, cnn_hi=0.98)
-    Mc = gctx.occl_detect(D, angles, ratios, prm)
-    c = gctx.occl_confusion(Mc, M)
-    iou = c["tp"] / max(1, c["tp"] + c["fp"] + c["fn"])
-    assert iou >= 0.98, c
+    tp = fp = fn = 0
+    for seed in (4100, 4101, 4115):
+        sc = scenes.make_c1_like(seed, W=1920, H=1080)
+        D = to_dev(torch, sc.D)
+        M = gctx.occl_detect(D, angles, ratios, occl.params(scan_len_per_view=sc.scan_len))
+        prm = occl.params(scan_len_per_view=sc.scan_len, flags=occl.FLAG_USE_CNN | occl.FLAG_SYNC)
+        assert (prm.cnn_lo, prm.cnn_hi) == pytest.approx((0.05, 0.95))
+        Mc = gctx.occl_detect(D, angles, ratios, prm)
+        c = gctx.occl_confusion(Mc, M)
+        tp, fp, fn = tp + c["tp"], fp + c["fp"], fn + c["fn"]
+    iou = tp / max(1, tp + fp + fn)
+    record_property("iou_band_0.05_0.95", iou)
+    assert iou >= 0.99, (tp, fp, fn)
+
+    def timed(p, reps=30):
+        for _ in range(3):
+            gctx.occl_detect(D, angles, ratios, p, M=M)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            gctx.occl_detect(D, angles, ratios, p, M=M)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_exact = timed(occl.params(scan_len_per_view=sc.scan_len))
+    t_cnn = timed(occl.params(scan_len_per_view=sc.scan_len, flags=occl.FLAG_USE_CNN))
+    ratio = t_exact / t_cnn
+    record_property("speed_vs_exact", ratio)
+    print(f"CNN + fallback: IoU {iou:.5f} at [0.05, 0.95]; {t_cnn * 1e3:.4f} ms against "
+          f"{t_exact * 1e3:.4f} ms exact, speed ratio {ratio:.3f} (target > 1: not met)", flush=True)
+    assert ratio > 0
 
 
 @pytest.mark.parametrize("shape", [(192, 256), (61, 83), (1080, 1920), (17, 300), (1, 1)])
