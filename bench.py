@@ -492,11 +492,24 @@ def bench_c1(args):
     for _ in range(args.prewarm):
         det(D, M)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        det(D, M)
-    torch.cuda.synchronize()
-    single_ms = (time.perf_counter() - t0) * 1e3 / steps
+
+    def median_ms(fn, n, windows=5):
+        """Median over windows of n steps: a one-off host or runtime stall
+        (the HIP runtime pauses once some thousand launches into a process)
+        must not set the figure."""
+        per = []
+        for _ in range(windows):
+            t0 = time.perf_counter()
+            fn(n)
+            torch.cuda.synchronize()
+            per.append((time.perf_counter() - t0) * 1e3 / n)
+        return sorted(per)[len(per) // 2], per
+
+    def single(n):
+        for _ in range(n):
+            det(D, M)
+
+    single_ms, single_w = median_ms(single, max(1, steps // 5))
     # frames in flight: one context (workspace) and one output per HIP stream
     S = max(1, args.streams)
     fl_streams = [torch.cuda.Stream() for _ in range(S)]
@@ -519,10 +532,7 @@ def bench_c1(args):
         fl_shape = tune_in_flight(fl_ctxs, run)
     run(args.prewarm)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run(steps)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    ms_fl, fl_w = median_ms(run, max(1, steps // 5))
     fl_bad = sum(int((m != M).sum().item()) for m in fl_Ms)
     for c in fl_ctxs:
         c.occl_release()
@@ -534,12 +544,13 @@ def bench_c1(args):
     n_cand = ctx.occl_last_candidate_counts(V)
     scan_rep = ctx.occl_time_scanlines(200)
     alg = (4 + V) * H * W
-    ms_fl = elapsed * 1e3 / steps
     out = {"workload": C1_WORKLOAD, "frames_in_flight": S, "in_flight_launch_shape": fl_shape,
            "ms_per_frame": round(ms_fl, 5), "value": round(H * W * V / (ms_fl * 1e-3) / 1e6, 1),
+           "windows_ms": [round(x, 5) for x in fl_w],
            "hbm_frac": round(alg / (ms_fl * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
            "single_stream": {"ms_per_frame": round(single_ms, 5),
-                             "value": round(H * W * V / (single_ms * 1e-3) / 1e6, 1)},
+                             "value": round(H * W * V / (single_ms * 1e-3) / 1e6, 1),
+                             "windows_ms": [round(x, 5) for x in single_w]},
            "stages_ms": {k: round(prof[k][0] / max(1, prof[k][1]), 5) for k in ("edges", "scanlines")},
            "scanline_pass_ms": round(scan_rep, 5), "launch_shape": tune,
            "scanline_hbm_frac": round(alg / (scan_rep * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
