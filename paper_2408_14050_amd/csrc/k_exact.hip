@@ -1285,13 +1285,21 @@ __global__ __launch_bounds__(64 * batched_waves_per_block<KMAX>(), min_waves_per
 // ---------------------------------------------------------------------------
 // Fused pass: Eqs. (1)-(6) of every view of one tile of kFusedRows x 256
 // pixels in one block, for frames whose views all have scanlines of at most
-// 128 samples (plain form).  The block loads the tile (one wavefront per
-// row, as the edge pass), keeps the candidates of every view in an LDS
-// queue, and its wavefronts run those scanlines right away, gathering D
-// from global memory.  No candidate list, list counter, prefix or second
-// launch is involved.  Hits are byte stores of 1 into masks that a fill
-// kernel has cleared before the pass (a scanline can write up to h pixels
-// outside its tile, so the tile cannot clear its own pixels).
+// 128 samples (plain form).  Per tile:
+//   1. the block loads the tile (one wavefront per row, as the edge pass),
+//      applies Eq. (1) and the magnitude half of Eq. (2), and compacts the
+//      strong pixels (with their differences) into LDS;
+//   2. one lane per strong pixel applies the direction half of Eq. (2) for
+//      every view and appends the candidates to an LDS queue, so the
+//      per-view work scales with the strong pixels, not with the tile;
+//   3. the wavefronts take queue entries as they finish their previous one
+//      and run those scanlines, gathering D from global memory.
+// A tile with more strong pixels than the queue holds for all views runs 2
+// and 3 in rounds over slices of its strong pixels.  No candidate list,
+// list counter, prefix or second launch is involved.  Hits are byte stores
+// of 1 into masks that a fill kernel has cleared before the pass (a
+// scanline can write up to h pixels outside its tile, so the tile cannot
+// clear its own pixels).
 // Tiles are handed out by tickets: the flat tile list of the launch is cut
 // into kFusedParts contiguous parts, block b starts on part b % kFusedParts
 // (blocks are dealt to the 8 dies in turn, so each die mostly works on one
@@ -1304,11 +1312,12 @@ template <int ROWS>
 struct FusedShared {
     static constexpr int kQueue = ROWS * kEdgeCols;  // candidate entries per round (the tile's pixels)
     uint32_t queue[kQueue];       // (v << 12) | (row << 8) | column of the tile
-    int cnt[OCCL_MAX_VIEWS];      // candidates per view in the tile
+    uint16_t spix[kQueue];        // strong pixels: (row << 8) | column
+    int ns;                       // strong pixels of the tile
     int qn;                       // entries in the queue
     int take;                     // entries handed to wavefronts
-    int tile;                     // the block's current tile (-1: done)
-    int next;                     // the next one (fetched while the current one runs)
+    int tile, fi;                 // the block's current tile (-1: done) and its frame
+    int next, next_fi;            // the next ones (fetched while the current one runs)
 };
 
 // Next tile for block `part0`'s thread 0: tickets of part p run from
@@ -1324,11 +1333,26 @@ __device__ __forceinline__ int fused_ticket(unsigned* tickets, const int* pbeg, 
     return -1;
 }
 
+// Frame of flat tile t: the last frame whose first tile is at most t.
+__device__ __forceinline__ int fused_frame_of(const int* begin, int n_frames, int t) {
+    int a = 0, b = n_frames - 1;
+    while (a < b) {
+        const int mid = (a + b + 1) >> 1;
+        if (begin[mid] <= t) a = mid; else b = mid - 1;
+    }
+    return a;
+}
+
 // One tile (bx, by) of frame f.  Every thread of the block calls it.
+// exy: kQueue entries of LDS free until the first scanline of the tile (the
+// scanline scratch), holding the strong pixels' differences meanwhile.
+// On entry S.qn and S.take are 0 and S.ns holds no other tile's pixels; on
+// return S.ns is 0 again and S.qn, S.take are cleared by the caller after
+// the block's next barrier.
 template <int ROWS>
 __device__ __forceinline__ void fused_tile(const FrameDesc& f, int bx, int by, int n_views, const ViewTable& vt,
                                            const Thresholds& th, const WaveLds& L, FusedShared<ROWS>& S,
-                                           int wave, int lane) {
+                                           float2* exy, int wave, int lane) {
     constexpr int kQ = FusedShared<ROWS>::kQueue;
     const int H = f.H, W = f.W;
     const int y = by * ROWS + wave;
@@ -1349,49 +1373,66 @@ __device__ __forceinline__ void fused_tile(const FrameDesc& f, int bx, int by, i
             strong |= (live && (x0 + j < W) && (q >= th.q_min)) ? (1u << j) : 0u;
         }
     }
-    auto cand = [&](int v, int j) {  // the direction half of Eq. (2)
-        const float dot = __fadd_rn(__fmul_rn(ex[j], vt.c[v]), __fmul_rn(ey[j], vt.s[v]));
-        return ((strong >> j) & 1u) && (dot > 0.0f);
-    };
-    const bool any = __ballot(strong != 0) != 0;
-    // candidates per view
-    if (any) {
-        for (int v = 0; v < n_views; ++v) {
-            int tot = 0;
+    // 1. the strong pixels and their differences
+    {
+        uint64_t b[4];
+        int tot = 0, off = 0;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) tot += __popcll(__ballot(cand(v, j)));
-            if (lane == 0 && tot) atomicAdd(&S.cnt[v], tot);
+        for (int j = 0; j < 4; ++j) {
+            b[j] = __ballot((strong >> j) & 1u);
+            tot += __popcll(b[j]);
+            off += (int)lanes_below(b[j]);
+        }
+        if (tot) {  // uniform
+            int base = 0;
+            if (lane == 0) base = atomicAdd(&S.ns, tot);
+            int i = __builtin_amdgcn_readfirstlane(base) + off;
+            const uint32_t p0 = ((uint32_t)wave << 8) | (uint32_t)(lane * 4);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if ((strong >> j) & 1u) {
+                    S.spix[i] = (uint16_t)(p0 + (uint32_t)j);
+                    exy[i] = make_float2(ex[j], ey[j]);
+                    ++i;
+                }
+            }
         }
     }
     __syncthreads();
-    int va = 0;
-    while (va < n_views) {
-        // the views of this round: as many as the queue holds (one view always fits)
-        int vb = va, acc = 0;
-        while (vb < n_views && acc + S.cnt[vb] <= kQ) acc += S.cnt[vb++];
-        if (any) {
-            for (int v = va; v < vb; ++v) {
-                uint64_t b[4];
-                int tot = 0, off = 0;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    b[j] = __ballot(cand(v, j));
-                    tot += __popcll(b[j]);
-                    off += (int)lanes_below(b[j]);
-                }
-                if (tot == 0) continue;  // uniform
+    const int ns = S.ns;
+    const int per = kQ / n_views;  // strong pixels per round: their candidates fit the queue
+    for (int pa = 0; pa < ns; pa += per) {
+        const int pb = min(ns, pa + per);
+        // 2. the direction half of Eq. (2), one lane per strong pixel
+        for (int i0 = pa + wave * 64; i0 < pb; i0 += ROWS * 64) {
+            const int i = i0 + lane;
+            const bool ok = i < pb;
+            const uint32_t p = S.spix[ok ? i : pa];
+            float gx, gy;
+            if (pa == 0) {
+                const float2 g = exy[ok ? i : 0];
+                gx = g.x;
+                gy = g.y;
+            } else {  // the scanlines of the first round used exy: from D again
+                const int py = by * ROWS + (int)(p >> 8), px = bx * kEdgeCols + (int)(p & 255u);
+                const float* d = f.D + (size_t)py * W + px;
+                const float d0 = d[0];
+                gx = (px + 1 < W) ? __fsub_rn(d[1], d0) : 0.0f;
+                gy = (py + 1 < H) ? __fsub_rn(d[W], d0) : 0.0f;
+            }
+            for (int v = 0; v < n_views; ++v) {
+                const float dot = __fadd_rn(__fmul_rn(gx, vt.c[v]), __fmul_rn(gy, vt.s[v]));
+                const bool c = ok && (dot > 0.0f);
+                const uint64_t bm = __ballot(c);
+                if (bm == 0) continue;  // uniform
                 int base = 0;
-                if (lane == 0) base = atomicAdd(&S.qn, tot);
+                if (lane == 0) base = atomicAdd(&S.qn, __popcll(bm));
                 base = __builtin_amdgcn_readfirstlane(base);
-                uint32_t* dst = S.queue + base + off;
-                const uint32_t e0 = ((uint32_t)v << 12) | ((uint32_t)wave << 8) | (uint32_t)(lane * 4);
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if ((b[j] >> lane) & 1ull) *dst++ = e0 + (uint32_t)j;
+                if (c) S.queue[base + (int)lanes_below(bm)] = ((uint32_t)v << 12) | p;
             }
         }
         __syncthreads();
-        // wavefronts take entries as they finish their previous one
+        // 3. wavefronts take entries as they finish their previous one
         const int nq = S.qn;
         for (;;) {
             int i = 0;
@@ -1410,14 +1451,16 @@ __device__ __forceinline__ void fused_tile(const FrameDesc& f, int bx, int by, i
             else
                 scanline_plain<2>(f.D, H, W, Mv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, n, th, L, lane);
         }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            S.qn = 0;
-            S.take = 0;
+        if (pa + per < ns) {  // another round: the queue is reused
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                S.qn = 0;
+                S.take = 0;
+            }
+            __syncthreads();
         }
-        va = vb;
-        if (va < n_views) __syncthreads();
     }
+    if (threadIdx.x == 0) S.ns = 0;  // every thread read ns before the barrier after step 2
 }
 
 // All frames of the launch (one for a single frame): a persistent grid
@@ -1433,37 +1476,44 @@ __global__ __launch_bounds__(64 * ROWS, 8) void k_fused(const FrameDesc* __restr
     __shared__ float2 lds[ROWS][2][128];
     __shared__ uint32_t okeys[ROWS][128];
     __shared__ int runs[ROWS][kMaxRunsCap + 1];
+    static_assert(sizeof(lds) / sizeof(float2) == FusedShared<ROWS>::kQueue, "exy spans the scanline scratch");
     for (int i = threadIdx.x; i < n_frames; i += blockDim.x) begin[i] = table[i].block_begin;
     if (threadIdx.x == 0) begin[n_frames] = total_tiles;
     if (threadIdx.x <= kFusedParts) pbeg[threadIdx.x] = (int)((long long)total_tiles * threadIdx.x / kFusedParts);
-    for (int v = threadIdx.x; v < n_views; v += blockDim.x) S.cnt[v] = 0;
     const int part0 = (int)(blockIdx.x % kFusedParts);
     int part = part0;  // thread 0's current part
+    __syncthreads();
     if (threadIdx.x == 0) {
+        S.ns = 0;
         S.qn = 0;
         S.take = 0;
         S.tile = fused_ticket(tickets, pbeg, part, part0);
+        S.fi = S.tile < 0 ? 0 : fused_frame_of(begin, n_frames, S.tile);
     }
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const WaveLds L{lds[wave][0], okeys[wave], lds[wave][1], runs[wave]};
-    int fi = 0;
     for (;;) {
         const int t = S.tile;
         if (t < 0) break;
-        if (threadIdx.x == 0) S.next = fused_ticket(tickets, pbeg, part, part0);
-        int a = 0, b = n_frames - 1;  // frame of tile t: last with begin <= t
-        while (a < b) {
-            const int mid = (a + b + 1) >> 1;
-            if (begin[mid] <= t) a = mid; else b = mid - 1;
+        const int fi = S.fi;
+        if (threadIdx.x == 0) {
+            // the previous tile's queue counters (every wavefront has passed
+            // the barrier that ended that tile) and the next ticket
+            S.qn = 0;
+            S.take = 0;
+            S.next = fused_ticket(tickets, pbeg, part, part0);
+            S.next_fi = S.next < 0 ? 0 : fused_frame_of(begin, n_frames, S.next);
         }
-        fi = a;
         const FrameDesc& f = table[fi];
         const int local = t - begin[fi];
-        fused_tile<ROWS>(f, local % f.gx, local / f.gx, n_views, vt, th, L, S, wave, lane);
-        if (threadIdx.x < n_views) S.cnt[threadIdx.x] = 0;
-        if (threadIdx.x == 0) S.tile = S.next;
+        fused_tile<ROWS>(f, local % f.gx, local / f.gx, n_views, vt, th, L, S, &lds[0][0][0], wave, lane);
+        // every thread read S.tile and S.fi before the tile's first barrier
+        if (threadIdx.x == 0) {
+            S.tile = S.next;
+            S.fi = S.next_fi;
+        }
         __syncthreads();
     }
 }

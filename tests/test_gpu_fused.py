@@ -91,11 +91,15 @@ def test_fused_ragged_frames_and_short_scanlines(torch, ref, seed):
         assert np.array_equal(T, R)
 
 
-def test_fused_dense_candidates_overflow_rounds(torch, ref):
-    """A ramp whose every pixel is a candidate of every view facing it: the
-    tile's candidates exceed one queue, so the views go in rounds."""
+@pytest.mark.parametrize("H,W", [(64, 600), (67, 601)])
+def test_fused_dense_candidates_overflow_rounds(torch, ref, H, W):
+    """A ramp whose every pixel is strong: a tile's strong pixels exceed
+    what one queue holds for all views, so they go in rounds, and the
+    rounds after the first take the differences from D again (at the
+    frame's right and bottom borders too, and with the scalar loads of a
+    width that is not a multiple of 4)."""
     from paper_2408_14050_amd import occl
-    H, W = 64, 600
+    print(f"fused dense {W}x{H}", flush=True)
     yy, xx = np.mgrid[0:H, 0:W]
     D = (1.5 * xx + 1.25 * yy + 0.01 * ((xx * 7 + yy * 13) % 11)).astype(np.float32) % 40.0
     angles, ratios = scenes.views_3x3()
