@@ -80,6 +80,22 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Loads of D and stores into the masks through global (not flat)
+// instructions: the pointers come from the frame table, so the compiler
+// cannot infer their address space, and flat accesses also count against
+// the LDS wait counter (an LDS wait would then wait for gathers in flight).
+__device__ __forceinline__ float ldg(const float* p) {
+    return *(const __attribute__((address_space(1))) float*)p;
+}
+__device__ __forceinline__ float4 ldg4(const float* p) {
+    typedef float f4 __attribute__((ext_vector_type(4)));  // float4's copy would take a generic reference
+    const f4 v = *(const __attribute__((address_space(1))) f4*)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void stg1(uint8_t* p) {
+    *(__attribute__((address_space(1))) uint8_t*)p = 1;
+}
+
 // LDS exchange inside one wavefront: keeps the compiler from moving LDS
 // accesses across this point (one wavefront's LDS operations are processed
 // in order by the hardware).
@@ -178,21 +194,21 @@ __device__ __forceinline__ EdgeIn edge_load(const FrameDesc& f, int bx, int by) 
         const float* row = f.D + (size_t)y * W;
         const bool next_row = (y + 1 < H);
         if (edge_vec(f)) {  // W % 4 == 0 and D 16-byte aligned, so x0 + 3 < W
-            const float4 a = *reinterpret_cast<const float4*>(row + x0);
+            const float4 a = ldg4(row + x0);
             in.d0[0] = a.x; in.d0[1] = a.y; in.d0[2] = a.z; in.d0[3] = a.w;
             if (next_row) {
-                const float4 b = *reinterpret_cast<const float4*>(row + W + x0);
+                const float4 b = ldg4(row + W + x0);
                 in.d1[0] = b.x; in.d1[1] = b.y; in.d1[2] = b.z; in.d1[3] = b.w;
             }
         } else {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const bool inside = (x0 + j < W);
-                in.d0[j] = inside ? row[x0 + j] : 0.0f;
-                in.d1[j] = (inside && next_row) ? row[W + x0 + j] : 0.0f;
+                in.d0[j] = inside ? ldg(row + x0 + j) : 0.0f;
+                in.d1[j] = (inside && next_row) ? ldg(row + W + x0 + j) : 0.0f;
             }
         }
-        in.dn = (x0 + 4 < W) ? row[x0 + 4] : 0.0f;
+        in.dn = (x0 + 4 < W) ? ldg(row + x0 + 4) : 0.0f;
     }
     return in;
 }
@@ -583,7 +599,7 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
             const float bot = __fadd_rn(__fmul_rn(gx, cc), __fmul_rn(fx, d));
             Vr = __fadd_rn(__fmul_rn(gy, top), __fmul_rn(fy, bot));
         } else {
-            Vr = D[valid ? po : 0u];  // a dropped sample reads pixel 0 and is discarded
+            Vr = ldg(D + (valid ? po : 0u));  // a dropped sample reads pixel 0 and is discarded
         }
         pofs[k] = po;  // used for kept samples only
         const float V = valid ? Vr : 0.0f;
@@ -766,7 +782,7 @@ __device__ __forceinline__ void order_test_lds(uint8_t* __restrict__ Mv, int W, 
             if constexpr (G)
                 mark_hit<K, G>(Mv, W, cx, cy, c, s, e - h, tv);
             else
-                Mv[pofs[k]] = 1;  // the pixel the gather read
+                stg1(Mv + pofs[k]);  // the pixel the gather read
         }
     }
     wave_lds_sync();
@@ -774,9 +790,10 @@ __device__ __forceinline__ void order_test_lds(uint8_t* __restrict__ Mv, int W, 
 
 // ---------------------------------------------------------------------------
 // Plain form (N = 1, nearest-pixel V, no routed tiles) of the scanlines of
-// at most 128 samples: samples, the one- and two-run orderings and the test
-// of Eq. (5) stay in registers; cross-lane traffic goes through DPP and
-// ds_bpermute, and only scanlines of three or more runs go through LDS.
+// at most 128 samples: the samples and the one-run test of Eq. (5) stay in
+// registers (neighbours through DPP); two runs take their sorted neighbours
+// from a binary search over the other run in LDS; three or more runs go
+// through the general LDS ordering.
 // ---------------------------------------------------------------------------
 // Wave-wide shift by one lane (DPP wave_shr:1 / wave_shl:1): lane i receives
 // v of lane i - 1 (up) or i + 1 (down); the lane that has no source lane
@@ -789,49 +806,6 @@ __device__ __forceinline__ float wave_down1(float v, float fill) {
     return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(v), 0x130, 0xF, 0xF,
                                                       false));
 }
-// v of lane `src & 63`
-__device__ __forceinline__ uint32_t lane_read(uint32_t v, int src) {
-    return (uint32_t)__builtin_amdgcn_ds_bpermute((src & 63) << 2, (int)v);
-}
-__device__ __forceinline__ float lane_readf(float v, int src) {
-    return __uint_as_float(lane_read(__float_as_uint(v), src));
-}
-// slot-crossing reads of a K-slot array: element e = 64 * k + lane
-template <int K>
-__device__ __forceinline__ uint32_t elem_read(const uint32_t (&v)[K], int e) {
-    if constexpr (K == 1) {
-        return lane_read(v[0], e);
-    } else {
-        const uint32_t a = lane_read(v[0], e), b = lane_read(v[1], e);
-        return (e & 64) ? b : a;
-    }
-}
-
-// One stage of an ascending bitonic merge of the 64 K keys (element e =
-// 64 k + lane in key[k]): e and e ^ stride swap when out of order.
-template <int K>
-__device__ __forceinline__ void merge_stage(uint64_t (&key)[K], int stride, int lane) {
-    if (stride >= 64) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if ((k & (stride >> 6)) == 0) {
-                const int kp = k | (stride >> 6);
-                const uint64_t a = key[k], b = key[kp];
-                const bool sw = b < a;
-                key[k] = sw ? b : a;
-                key[kp] = sw ? a : b;
-            }
-        }
-    } else {
-        const bool lower = (lane & stride) == 0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const uint64_t o = xchg64(key[k], stride, lane);
-            key[k] = ((o < key[k]) == lower) ? o : key[k];  // lower keeps the smaller, upper the larger
-        }
-    }
-}
-
 // Eq. (5) with one neighbour per side and Eq. (6) for sorted positions q =
 // 64 k + lane holding (W, V) of the sample whose pixel offset is po; W NaN
 // marks a position without a sample.
@@ -850,8 +824,76 @@ __device__ __forceinline__ void test_sorted(uint8_t* __restrict__ Mv, const floa
         const float vr = wave_down1(v[k], k + 1 < K ? lanef(v[kn], 0) : 0.0f);
         const bool hit = ((fabsf(__fsub_rn(w[k], wl)) < th.zeta) & (__fsub_rn(vl, v[k]) > th.beta)) |
                          ((fabsf(__fsub_rn(w[k], wr)) < th.zeta) & (__fsub_rn(vr, v[k]) > th.beta));
-        if (hit) Mv[po[k]] = 1;  // a NaN W (no sample here) never hits
+        if (hit) stg1(Mv + po[k]);  // a NaN W (no sample here) never hits
     }
+}
+
+// Two runs A = [e_lo, j0) and B = [j0, e_hi] (each non-decreasing in W; e_lo
+// < j0 <= e_hi): the sorted order of (W, e) interleaves them, so the sorted
+// predecessor of a sample is the later of its predecessor in its own run and
+// the last sample of the other run before it, and its successor is the
+// earlier of its successor in its own run and the first sample of the other
+// run after it.  That rank in the other run comes from a binary search over
+// the other run's ord(W) keys (a sample of A precedes a sample of B of equal
+// W, as its offset is smaller), so neither a sorted array nor a merge is
+// built.  Then Eq. (5) with one neighbour per side and Eq. (6).
+// LDS: WVin holds (W, V) by offset; WVs holds the keys of A and of B from
+// index 0 each, padded with ~0 (above every key), 2 N words.
+template <int K>
+__device__ __forceinline__ void two_runs(uint8_t* __restrict__ Mv, const float (&wk)[K], const float (&vk)[K],
+                                         const bool (&kept)[K], const uint32_t (&pofs)[K], int e_lo, int j0,
+                                         int e_hi, const Thresholds& th, const WaveLds& L, int lane) {
+    constexpr int N = 64 * K;
+    uint32_t* OA = reinterpret_cast<uint32_t*>(L.WVs);
+    uint32_t* OB = OA + N;
+    const int lenA = j0 - e_lo, lenB = e_hi - j0 + 1;
+    uint32_t key[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int e = k * 64 + lane;
+        OA[e] = ~0u;
+        OB[e] = ~0u;
+        L.WVin[e] = make_float2(wk[k], vk[k]);
+        key[k] = f2ord(wk[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {  // after the padding (same addresses, program order)
+        const int e = k * 64 + lane;
+        if (kept[k]) {
+            if (e < j0) OA[e - e_lo] = key[k];
+            else OB[e - j0] = key[k];
+        }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int e = k * 64 + lane;
+        const bool inA = e < j0;
+        const uint32_t* O = inA ? OB : OA;
+        const int olen = inA ? lenB : lenA;
+        const int obase = inA ? j0 : e_lo;
+        // rank r: samples of the other run before (W_e, e)
+        const uint32_t T = key[k] + (inA ? 0u : 1u);
+        int r = 0;
+#pragma unroll
+        for (int step = N / 2; step >= 1; step >>= 1) r = (O[r + step - 1] < T) ? r + step : r;
+        const int lo_own = inA ? e_lo : j0, hi_own = inA ? j0 - 1 : e_hi;
+        const float2 pw = L.WVin[max(e - 1, lo_own)];        // own run, e - 1
+        const float2 nw = L.WVin[min(e + 1, hi_own)];        // own run, e + 1
+        const float2 po = L.WVin[obase + max(r - 1, 0)];     // other run, rank r - 1
+        const float2 no = L.WVin[obase + min(r, olen - 1)];  // other run, rank r
+        const bool hpw = e > lo_own, hnw = e < hi_own, hpo = r > 0, hno = r < olen;
+        // the later predecessor and the earlier successor in (W, e) order
+        const bool po_later = (po.x > pw.x) || (inA && po.x == pw.x);
+        const bool nw_first = (nw.x < no.x) || (inA && nw.x == no.x);
+        const float2 P = (hpo && (!hpw || po_later)) ? po : pw;
+        const float2 S = (hnw && (!hno || nw_first)) ? nw : no;
+        const float w = wk[k], v = vk[k];
+        const bool hit = ((hpw || hpo) & (fabsf(__fsub_rn(w, P.x)) < th.zeta) & (__fsub_rn(P.y, v) > th.beta)) |
+                         ((hnw || hno) & (fabsf(__fsub_rn(w, S.x)) < th.zeta) & (__fsub_rn(S.y, v) > th.beta));
+        if (kept[k] & hit) stg1(Mv + pofs[k]);
+    }
+    wave_lds_sync();
 }
 
 template <int K>
@@ -873,7 +915,7 @@ __device__ __forceinline__ void scanline_plain(const float* __restrict__ D, int 
         const int iy = (int)rintf(__fadd_rn((float)cy, __fmul_rn(s, gf)));
         const bool valid = (e < n) & ((uint32_t)ix < (uint32_t)W) & ((uint32_t)iy < (uint32_t)H);
         const uint32_t po = (uint32_t)iy * (uint32_t)W + (uint32_t)ix;  // H * W < 2^32
-        const float Vr = D[valid ? po : 0u];  // a dropped sample reads pixel 0 and is discarded
+        const float Vr = ldg(D + (valid ? po : 0u));  // a dropped sample reads pixel 0 and is discarded
         pofs[k] = po;
         vk[k] = valid ? Vr : 0.0f;
         wk[k] = valid ? __fsub_rn(gf, __fmul_rn(r, Vr)) : NaN;
@@ -907,45 +949,11 @@ __device__ __forceinline__ void scanline_plain(const float* __restrict__ D, int 
         return;
     }
     if (ndesc == 1) {
-        // two runs A = [e_lo, j0) and B = [j0, e_hi]: keys (ord(W), e) of A in
-        // place, padded below by 0, and B reversed at the top, padded by ~0,
-        // form a bitonic sequence; a bitonic merge sorts it, and the kept
-        // samples then sit at positions e_lo .. e_hi
-        int j0 = 0;
+        int j0 = 0;  // the descent: B's first offset
 #pragma unroll
         for (int k = 0; k < K; ++k)
             if (dm[k]) j0 = k * 64 + __ffsll((unsigned long long)dm[k]) - 1;
-        const int lenB = e_hi - j0 + 1;
-        uint32_t wbits[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) wbits[k] = __float_as_uint(wk[k]);
-        uint64_t key[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int q = k * 64 + lane;
-            const int src = e_hi + N - lenB - q;  // B reversed: q in [N - lenB, N)
-            const float wB = __uint_as_float(elem_read<K>(wbits, src));
-            const uint64_t kA = ((uint64_t)f2ord(wk[k]) << 32) | (uint32_t)q;
-            const uint64_t kB = ((uint64_t)f2ord(wB) << 32) | (uint32_t)src;
-            key[k] = q < e_lo ? 0ull : (q < j0 ? kA : (q < N - lenB ? ~0ull : kB));
-        }
-#pragma unroll
-        for (int st = N / 2; st >= 1; st >>= 1) merge_stage<K>(key, st, lane);
-        uint32_t vbits[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) vbits[k] = __float_as_uint(vk[k]);
-        float ws[K], vs[K];
-        uint32_t po[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int q = k * 64 + lane;
-            const bool real = (q >= e_lo) & (q <= e_hi);
-            const int e = (int)(uint32_t)key[k];
-            ws[k] = real ? ord2f((uint32_t)(key[k] >> 32)) : NaN;
-            vs[k] = __uint_as_float(elem_read<K>(vbits, e));
-            po[k] = elem_read<K>(pofs, e);
-        }
-        test_sorted<K>(Mv, ws, vs, po, th);
+        two_runs<K>(Mv, wk, vk, kept, pofs, e_lo, j0, e_hi, th, L, lane);
         return;
     }
     // three or more runs: through LDS
@@ -1416,9 +1424,9 @@ __device__ __forceinline__ void fused_tile(const FrameDesc& f, int bx, int by, i
             } else {  // the scanlines of the first round used exy: from D again
                 const int py = by * ROWS + (int)(p >> 8), px = bx * kEdgeCols + (int)(p & 255u);
                 const float* d = f.D + (size_t)py * W + px;
-                const float d0 = d[0];
-                gx = (px + 1 < W) ? __fsub_rn(d[1], d0) : 0.0f;
-                gy = (py + 1 < H) ? __fsub_rn(d[W], d0) : 0.0f;
+                const float d0 = ldg(d);
+                gx = (px + 1 < W) ? __fsub_rn(ldg(d + 1), d0) : 0.0f;
+                gy = (py + 1 < H) ? __fsub_rn(ldg(d + W), d0) : 0.0f;
             }
             for (int v = 0; v < n_views; ++v) {
                 const float dot = __fadd_rn(__fmul_rn(gx, vt.c[v]), __fmul_rn(gy, vt.s[v]));
