@@ -57,16 +57,19 @@ occl_status occl_ctx::enqueue_batch(int n_frames, const occl_frame* frames, int 
     const uint64_t bucket = tune_key(true, px, n_views, maxcls);
     TuneConfig tc = cfg ? *cfg : config_for(bucket);
     // edge_rows 0 selects the fused pass where the batch allows it.  Without
-    // a measured shape for the bucket, batches of at least 16 tiles per
-    // resident block take it (64 mixed frames: 1.40 ms against 1.58-1.61 ms
-    // for the two passes); smaller ones keep the two passes (16 frames of
-    // 1280x960: 0.42 ms fused against 0.35 ms).
+    // a measured shape for the bucket, batches of at least 8 tiles per
+    // resident block take it.  A block's tile is done when its busiest
+    // wavefront is, so a batch of few tiles waits on its tiles with the most
+    // candidates, while the two passes spread the candidates over the whole
+    // grid: 16 mixed frames (about 6,800 tiles) 0.32 ms fused against 0.43 ms,
+    // 12 frames of 1280x960 (3,600 tiles) 0.29 against 0.28 ms, one such
+    // frame 0.096 against 0.046 ms.
     if (!cfg && tuned.find(bucket) == tuned.end()) {
         long long tiles = 0;
         for (int f = 0; f < n_frames; ++f)
             tiles += (long long)((frames[f].W + kEdgeCols - 1) / kEdgeCols) *
                      ((frames[f].H + kFusedTileRows - 1) / kFusedTileRows);
-        if (tiles >= 16ll * n_cu * fused_blocks_per_cu()) tc.edge_rows = 0;
+        if (tiles >= 8ll * n_cu * fused_blocks_per_cu()) tc.edge_rows = 0;
     }
     if (tc.edge_rows == 0) {
         if (fusable(n_views, maxcls, th)) return enqueue_batch_fused(n_frames, frames, n_views, Ls_all, vt, th);
