@@ -61,9 +61,9 @@ occl_status occl_ctx::enqueue_batch(int n_frames, const occl_frame* frames, int 
     // resident block take it.  A block's tile is done when its busiest
     // wavefront is, so a batch of few tiles waits on its tiles with the most
     // candidates, while the two passes spread the candidates over the whole
-    // grid: 16 mixed frames (about 6,800 tiles) 0.32 ms fused against 0.43 ms,
+    // grid: 16 mixed frames (5,642 tiles) 0.32 ms fused against 0.43 ms,
     // 12 frames of 1280x960 (3,600 tiles) 0.29 against 0.28 ms, one such
-    // frame 0.096 against 0.046 ms.
+    // frame 0.11 against 0.05 ms.
     if (!cfg && tuned.find(bucket) == tuned.end()) {
         long long tiles = 0;
         for (int f = 0; f < n_frames; ++f)
