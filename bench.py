@@ -208,7 +208,7 @@ C1_WORKLOAD = "c1 1280x960 x8 views seed 1002"
 C2_WORKLOAD = "c2 3840x2160 x15 views seed 2000"
 FUSED_KERNEL = "k_fused<16>"  # the fused pass at its tile height (rows per tile)
 C2_PROFILE_CMD = "rocprofv3 {mode} -d gpurun_out/{out} -o run -- python3 bench.py --c2-only --c2-steps 5"
-C2_KERNELS = ("k_edges<0>", "k_scanlines<4, 0>", "k_scanlines<8, 0>")
+C2_KERNELS = ("k_edges", "k_scanlines<4, 0>", "k_scanlines<8, 0>")
 QUALITY_WORKLOAD = "c1 1280x960 x8 views seeds 1000-1003"
 LEARNED_WORKLOAD = "c4 1920x1080 x8 views seed 4100"
 THIN_WORKLOAD = "c1 1280x960 x8 views seed 1002 thinned"

@@ -237,8 +237,9 @@ occl_status occl_quality(occl_ctx* ctx, const uint8_t* pred, const uint8_t* ref,
  * Not part of the paper: a small network proposes, per 16 x 16 pixel tile
  * and view, the probability that the tile holds occluded pixels (the tile's
  * occluded fraction of the exact mask of Sec. 3 is its training target).
- * Confident tiles are filled, the rest take the exact path of Sec. 3
- * restricted to them.  Network: six 3x3 convolutions 8->32 (stride 2),
+ * Confident tiles are filled, the rest keep the mask of the exact path of
+ * Sec. 3 (run over the frame: confident tiles hold no candidates in
+ * practice, so restricting it saves nothing).  Network: six 3x3 convolutions 8->32 (stride 2),
  * 32->32 (2), 32->32 (2), 32->32 (2), 32->32 (1), 32->1 (1), ReLU after all
  * but the last; bf16 weights and activations, fp32 accumulation and logits.
  * Parameters are one flat fp32 vector, layer by layer, each layer's weights
@@ -358,7 +359,7 @@ occl_status occl_release(occl_ctx* ctx);
 #define OCCL_STAGE_EDGES 0      /* k_edges_candidates: Eqs. (1)-(2) + mask clear */
 #define OCCL_STAGE_SCANLINES 1  /* k_scanlines: Eqs. (4)-(6) */
 #define OCCL_STAGE_CNN 2        /* learned tile proposal (pack, convolutions, routing) */
-#define OCCL_STAGE_FALLBACK 3   /* exact fallback on uncertain tiles */
+#define OCCL_STAGE_FALLBACK 3   /* routing: tile states, exact path, confident tiles' fill */
 #define OCCL_STAGE_BATCHED 4    /* one graph launch of occl_detect_batched */
 #define OCCL_N_STAGES 5
 occl_status occl_profile_enable(occl_ctx* ctx, int32_t enable);

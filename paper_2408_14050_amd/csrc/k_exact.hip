@@ -29,9 +29,9 @@
 //                    are byte stores of 1 into the cleared mask, so
 //                    concurrent scanlines need no atomics and the result
 //                    does not depend on order.
-// Each pass has a plain form (the exact path with N = 1, no bilinear
-// sampling, no routed tiles) and a general form with those runtime checks;
-// the host picks the plain one whenever a call allows it.
+// The scanline pass has a plain form (N = 1, nearest-pixel sampling, no
+// thinning) and a general form with those runtime checks; the host picks the
+// plain one whenever a call allows it.
 //
 // Every fp32 operation that feeds a decision is an explicitly rounded
 // intrinsic (__fmul_rn, __fadd_rn, __fsub_rn) and the library is built with
@@ -213,9 +213,7 @@ __device__ __forceinline__ EdgeIn edge_load(const FrameDesc& f, int bx, int by) 
     return in;
 }
 
-// kRouted: the frame may carry tile states / a reach map (routed exact
-// fallback); 0 compiles those lookups out of the plain path.
-template <bool kFinish, int kRouted>
+template <bool kFinish>
 __device__ void edge_block(const FrameDesc& f, int bx, int by, int n_views, const ViewTable& vt,
                            float q_min, const EdgeIn& in) {
     const int H = f.H, W = f.W;
@@ -244,24 +242,19 @@ __device__ void edge_block(const FrameDesc& f, int bx, int by, int n_views, cons
             strong[j] = live && (x < W) && (q >= q_min);
             any |= strong[j];
         }
-        // Every mask byte of the segment starts at 0 (a routed frame's filled
-        // tiles at their fill value).  The stores are issued while the list
-        // reservation's atomic is in flight.
+        // Every mask byte of the segment starts at 0.  The stores are issued
+        // while the list reservation's atomic is in flight.
         auto clear_mask = [&]() {
             if (!live) return;
             const size_t HW = (size_t)H * W;
-            const int tiles_y = (H + kTile - 1) / kTile;
             for (int v = 0; v < n_views; ++v) {
                 uint8_t* mrow = f.M + v * HW + (size_t)y * W;
-                const uint8_t fill =
-                    (kRouted && f.tstate) ? (f.tstate[((size_t)v * tiles_y + y / kTile) * f.tiles_x + x0 / kTile] == 1)
-                             : 0;
                 if (vec) {
-                    *reinterpret_cast<uint32_t*>(mrow + x0) = 0x01010101u * fill;
+                    *reinterpret_cast<uint32_t*>(mrow + x0) = 0u;
                 } else {
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
-                        if (x0 + j < W) mrow[x0 + j] = fill;
+                        if (x0 + j < W) mrow[x0 + j] = 0;
                 }
             }
         };
@@ -283,16 +276,11 @@ __device__ void edge_block(const FrameDesc& f, int bx, int by, int n_views, cons
                     const int v = v0 + i;
                     if (v >= n_views) continue;  // uniform
                     const float c = vt.c[v], s = vt.s[v];
-                    // routed frames keep only candidates that can reach an exact
-                    // tile (x0 .. x0 + 3 share one tile)
-                    const bool near =
-                        !kRouted || !f.tnear || (live && f.tnear[((size_t)v * ((H + kTile - 1) / kTile) + y / kTile) *
-                                                         f.tiles_x + x0 / kTile]);
                     uint64_t b[4];
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const float dot = __fadd_rn(__fmul_rn(ex[j], c), __fmul_rn(ey[j], s));
-                        const bool cand = strong[j] && (dot > 0.0f) && near;
+                        const bool cand = strong[j] && (dot > 0.0f);
                         m4all |= cand ? (1u << (4 * i + j)) : 0u;
                         b[j] = __ballot(cand);
                     }
@@ -365,10 +353,9 @@ __device__ void edge_block(const FrameDesc& f, int bx, int by, int n_views, cons
 // the next frame's edge blocks then share the CUs with the current frame's
 // scanline blocks more readily (c1, three frames in flight: 18.0-19.1 ->
 // 17.0 us per frame).
-template <int kRouted>
 __global__ __launch_bounds__(64 * kMaxEdgeRows, 8) void k_edges(FrameDesc f, int n_views, ViewTable vt,
                                                                float q_min) {
-    edge_block<true, kRouted>(f, blockIdx.x, blockIdx.y, n_views, vt, q_min, edge_load(f, blockIdx.x, blockIdx.y));
+    edge_block<true>(f, blockIdx.x, blockIdx.y, n_views, vt, q_min, edge_load(f, blockIdx.x, blockIdx.y));
 }
 
 // Every frame of a batch: a persistent grid walks the flat list of edge-pass
@@ -409,7 +396,7 @@ __global__ __launch_bounds__(64 * kMaxEdgeRows, 8) void k_edges_batched(
             nxt = edge_load(table[nfi], nlocal % table[nfi].gx, nlocal / table[nfi].gx);
         }
         const FrameDesc& f = table[fi];
-        edge_block<false, 0>(f, local % f.gx, local / f.gx, n_views, vt, q_min, cur);  // never routed
+        edge_block<false>(f, local % f.gx, local / f.gx, n_views, vt, q_min, cur);
         vb = nvb;
         fi = nfi;
         local = nlocal;
@@ -489,24 +476,16 @@ __device__ __forceinline__ bool key_less(float wa, int ea, float wb, int eb) {
     return wa < wb || (wa == wb && ea < eb);
 }
 
-// Tile states of one view of a routed frame (t == NULL: plain exact path).
-struct TileView {
-    const uint8_t* t;
-    int tiles_x;
-};
-
 // G (all scanline forms): 1 when the call may use the bilinear sampling
-// variant, a routed frame's tile states or more than one neighbour per side
-// (runtime checks), 0 for the plain exact path with N = 1, where those checks
+// variant, thinning or more than one neighbour per side (runtime checks), 0 for the plain exact path with N = 1, where those checks
 // are compiled out (fewer registers: c2 pass 2.93 -> 2.64 ms, c1 25.8 ->
 // 25.3 us).
 template <int K, int G>
 __device__ __forceinline__ void mark_hit(uint8_t* __restrict__ Mv, int W, int cx, int cy, float c,
-                                         float s, int g, TileView tv) {
+                                         float s, int g) {
     const float gf = (float)g;
     const int ix = (int)rintf(__fadd_rn((float)cx, __fmul_rn(c, gf)));
     const int iy = (int)rintf(__fadd_rn((float)cy, __fmul_rn(s, gf)));
-    if (G && tv.t && tv.t[(iy / kTile) * tv.tiles_x + ix / kTile] != 2) return;  // filled tile
     Mv[(size_t)iy * W + ix] = 1;
 }
 
@@ -556,7 +535,7 @@ __device__ __forceinline__ int thin_window(const float* __restrict__ D, int H, i
 }
 
 template <int K, int G>
-__device__ __forceinline__ void order_test_lds(uint8_t* __restrict__ Mv, int W, TileView tv, int cx, int cy,
+__device__ __forceinline__ void order_test_lds(uint8_t* __restrict__ Mv, int W, int cx, int cy,
                                                float c, float s, int h, const Thresholds& th,
                                                const WaveLds& L, int lane, const float (&wk)[K],
                                                const float (&vk)[K], const uint64_t (&vmask)[K],
@@ -566,7 +545,7 @@ __device__ __forceinline__ void order_test_lds(uint8_t* __restrict__ Mv, int W, 
 // (n = 2h + 1, or a thinning head's merged window).
 template <int K, int G>
 __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int W,
-                                         uint8_t* __restrict__ Mv, TileView tv, int cx, int cy, float c,
+                                         uint8_t* __restrict__ Mv, int cx, int cy, float c,
                                          float s, float r, int h, int n, const Thresholds& th,
                                          const WaveLds& L, int lane) {
     float wk[K], vk[K];  // this lane's W and V of slot k
@@ -612,14 +591,14 @@ __device__ __forceinline__ void scanline(const float* __restrict__ D, int H, int
         kept[k] = valid;
     }
     wave_lds_sync();
-    order_test_lds<K, G>(Mv, W, tv, cx, cy, c, s, h, th, L, lane, wk, vk, vmask, kept, pofs);
+    order_test_lds<K, G>(Mv, W, cx, cy, c, s, h, th, L, lane, wk, vk, vmask, kept, pofs);
 }
 
 // Ordering (Eq. (4)'s sort) and Eqs. (5)-(6) of one scanline whose samples
 // sit in registers (wk, vk, kept, pofs, vmask of slot k = offsets k*64 +
 // lane) and, by offset, in L.WVin / L.Oin.
 template <int K, int G>
-__device__ __forceinline__ void order_test_lds(uint8_t* __restrict__ Mv, int W, TileView tv, int cx, int cy,
+__device__ __forceinline__ void order_test_lds(uint8_t* __restrict__ Mv, int W, int cx, int cy,
                                                float c, float s, int h, const Thresholds& th,
                                                const WaveLds& L, int lane, const float (&wk)[K],
                                                const float (&vk)[K], const uint64_t (&vmask)[K],
@@ -780,7 +759,7 @@ __device__ __forceinline__ void order_test_lds(uint8_t* __restrict__ Mv, int W, 
         }
         if (valid & hit) {
             if constexpr (G)
-                mark_hit<K, G>(Mv, W, cx, cy, c, s, e - h, tv);
+                mark_hit<K, G>(Mv, W, cx, cy, c, s, e - h);
             else
                 stg1(Mv + pofs[k]);  // the pixel the gather read
         }
@@ -789,7 +768,7 @@ __device__ __forceinline__ void order_test_lds(uint8_t* __restrict__ Mv, int W, 
 }
 
 // ---------------------------------------------------------------------------
-// Plain form (N = 1, nearest-pixel V, no routed tiles) of the scanlines of
+// Plain form (N = 1, nearest-pixel V, no thinning) of the scanlines of
 // at most 128 samples: the samples and the one-run test of Eq. (5) stay in
 // registers (neighbours through DPP); two runs take their sorted neighbours
 // from a binary search over the other run in LDS; three or more runs go
@@ -964,8 +943,7 @@ __device__ __forceinline__ void scanline_plain(const float* __restrict__ D, int 
         L.Oin[e] = f2ord(wk[k]);
     }
     wave_lds_sync();
-    TileView tv{nullptr, 0};
-    order_test_lds<K, 0>(Mv, W, tv, cx, cy, c, s, h, th, L, lane, wk, vk, vmask, kept, pofs);
+    order_test_lds<K, 0>(Mv, W, cx, cy, c, s, h, th, L, lane, wk, vk, vmask, kept, pofs);
 }
 
 template <int KMAX>
@@ -1009,8 +987,6 @@ __device__ __forceinline__ void scan_item(const FrameDesc& f, int v, uint32_t pi
     const int cx = (int)(pix & 0xffffu);
     const int h = f.h[v];
     uint8_t* Mv = f.M + (size_t)v * H * W;
-    TileView tv{nullptr, f.tiles_x};
-    if (G && f.tstate) tv.t = f.tstate + (size_t)v * ((H + kTile - 1) / kTile) * f.tiles_x;
     int n = 2 * h + 1;
     if (G && th.thin && run_check) {
         n = thin_window(f.D, H, W, cx, cy, vt.c[v], vt.s[v], h, th.q_min, lane);
@@ -1025,11 +1001,11 @@ __device__ __forceinline__ void scan_item(const FrameDesc& f, int v, uint32_t pi
             scanline_plain<2>(f.D, H, W, Mv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, n, th, L, lane);
     } else if constexpr (KMAX == 2) {
         if (n <= 64)
-            scanline<1, G>(f.D, H, W, Mv, tv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, n, th, L, lane);
+            scanline<1, G>(f.D, H, W, Mv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, n, th, L, lane);
         else
-            scanline<2, G>(f.D, H, W, Mv, tv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, n, th, L, lane);
+            scanline<2, G>(f.D, H, W, Mv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, n, th, L, lane);
     } else {
-        scanline<KMAX, G>(f.D, H, W, Mv, tv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, n, th, L, lane);
+        scanline<KMAX, G>(f.D, H, W, Mv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, n, th, L, lane);
     }
 }
 
@@ -1584,9 +1560,6 @@ void describe_frame(FrameDesc* f, const float* D, uint8_t* M, int H, int W, int 
     f->gx = (W + kEdgeCols - 1) / kEdgeCols;
     f->gy = (H + edge_rows - 1) / edge_rows;
     f->block_begin = 0;
-    f->tstate = nullptr;
-    f->tnear = nullptr;
-    f->tiles_x = (W + kTile - 1) / kTile;
     for (int v = 0; v < OCCL_MAX_VIEWS; ++v) {
         f->h[v] = v < n_views ? Ls[v] / 2 : 0;
         f->vord[v] = 0;
@@ -1602,12 +1575,7 @@ void describe_frame(FrameDesc* f, const float* D, uint8_t* M, int H, int W, int 
 
 hipError_t launch_edges(hipStream_t st, const FrameDesc& f, int n_views, const ViewTable& vt,
                         float q_min) {
-    if (f.tstate || f.tnear)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_edges<1>), dim3(f.gx, f.gy), dim3(64 * f.ll.edge_rows), 0, st, f,
-                           n_views, vt, q_min);
-    else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_edges<0>), dim3(f.gx, f.gy), dim3(64 * f.ll.edge_rows), 0, st, f,
-                           n_views, vt, q_min);
+    hipLaunchKernelGGL(k_edges, dim3(f.gx, f.gy), dim3(64 * f.ll.edge_rows), 0, st, f, n_views, vt, q_min);
     return hipGetLastError();
 }
 
@@ -1692,12 +1660,12 @@ hipError_t launch_scanlines_batched_g(hipStream_t st, const FrameDesc* table, in
 
 hipError_t launch_scanlines(hipStream_t st, const FrameDesc& f, int n_views, const ViewTable& vt,
                             const Thresholds& th, int cls, int n_blocks) {
-    return (th.bilinear || th.thin || f.tstate || th.ns != 1)
+    return (th.bilinear || th.thin || th.ns != 1)
                ? launch_scanlines_g<1>(st, f, n_views, vt, th, cls, n_blocks)
                : launch_scanlines_g<0>(st, f, n_views, vt, th, cls, n_blocks);
 }
 
-// Batched frames are never routed (no tile states) and never thinned.
+// Batched frames are never thinned.
 int fused_blocks_per_cu() {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fused<kFusedTileRows>, 64 * kFusedTileRows, 0) !=

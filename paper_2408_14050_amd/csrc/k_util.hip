@@ -187,11 +187,6 @@ __global__ __launch_bounds__(256) void k_confusion_sum(const unsigned long long*
 // ---------------------------------------------------------------------------
 // tile routing
 // ---------------------------------------------------------------------------
-struct RouteViews {
-    float c[OCCL_MAX_VIEWS], s[OCCL_MAX_VIEWS];
-    int h[OCCL_MAX_VIEWS];
-};
-
 __global__ __launch_bounds__(256) void k_route_state(const float* __restrict__ z, long n, float z_lo,
                                                      float z_hi, uint8_t* __restrict__ st) {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
@@ -200,79 +195,27 @@ __global__ __launch_bounds__(256) void k_route_state(const float* __restrict__ z
     }
 }
 
-// Can a scanline from a pixel of tile (0, 0) sample a pixel of tile (dx, dy)?
-// A candidate C and its sample p = rint(C + u g), |g| <= h, differ by u g
-// plus at most 1/2 per axis (and fp32 rounding, covered by `slack`), while
-// pixels of the two tiles differ by 16 d +- 15 per axis: the segment
-// {u t : |t| <= h} must meet the box [16 dx +- (15.5 + slack)] x [16 dy +- ...].
-// The test is a superset (it may keep a few candidates that cannot reach).
-__device__ bool tile_reach(int dx, int dy, double c, double s, int h, double slack) {
-    double lo = -(double)h, hi = (double)h;
-    const double half = 15.5 + slack;
-    const double bx0 = 16.0 * dx - half, bx1 = 16.0 * dx + half;
-    const double by0 = 16.0 * dy - half, by1 = 16.0 * dy + half;
-    if (c == 0.0) {
-        if (bx0 > 0.0 || bx1 < 0.0) return false;
-    } else {
-        const double a = bx0 / c, b = bx1 / c;
-        lo = fmax(lo, fmin(a, b));
-        hi = fmin(hi, fmax(a, b));
-    }
-    if (s == 0.0) {
-        if (by0 > 0.0 || by1 < 0.0) return false;
-    } else {
-        const double a = by0 / s, b = by1 / s;
-        lo = fmax(lo, fmin(a, b));
-        hi = fmin(hi, fmax(a, b));
-    }
-    return lo <= hi;
-}
-
-// The reach stencil of each view: the tile offsets (dx, dy), |dx|, |dy| <= R,
-// that pass tile_reach, as packed (dy << 16 | dx & 0xffff) entries.
-// One block per view; entries [v * cap, v * cap + count[v]).
-__global__ __launch_bounds__(256) void k_route_stencil(RouteViews rv, double slack, int cap,
-                                                       int* __restrict__ count, int* __restrict__ st) {
-    __shared__ int n;
-    const int v = blockIdx.x;
-    const int h = rv.h[v];
-    const int R = (h + 16) / 16 + 1;
-    const int side = 2 * R + 1;
-    if (threadIdx.x == 0) n = 0;
-    __syncthreads();
-    for (int i = threadIdx.x; i < side * side; i += blockDim.x) {
-        const int dx = i % side - R, dy = i / side - R;
-        if (tile_reach(dx, dy, rv.c[v], rv.s[v], h, slack)) {
-            const int k = atomicAdd(&n, 1);
-            if (k < cap) st[(size_t)v * cap + k] = (int)(((unsigned)dy << 16) | ((unsigned)dx & 0xffffu));
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) count[v] = n < cap ? n : cap;
-}
-
-__global__ __launch_bounds__(256) void k_route_near(const uint8_t* __restrict__ state, int n_views,
-                                                    int tiles_y, int tiles_x, int cap,
-                                                    const int* __restrict__ count,
-                                                    const int* __restrict__ stencil,
-                                                    uint8_t* __restrict__ near) {
-    const long per = (long)tiles_y * tiles_x;
-    const long n = per * n_views;
+// Confident tiles of a routed frame take their state (0 or 1) in every mask
+// byte; exact tiles (state 2) keep what the exact path wrote there.  One
+// thread per 16-pixel row segment of a tile (consecutive threads: adjacent
+// segments of one row).
+__global__ __launch_bounds__(256) void k_route_apply(const uint8_t* __restrict__ state, int n_views, int H, int W,
+                                                     int tiles_y, int tiles_x, uint8_t* __restrict__ M) {
+    const long n = (long)n_views * H * tiles_x;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        const int v = (int)(i / per);
-        const int rem = (int)(i % per);
-        const int ty = rem / tiles_x, tx = rem % tiles_x;
-        const uint8_t* sv = state + (size_t)v * per;
-        const int* sl = stencil + (size_t)v * cap;
-        const int m = count[v];
-        uint8_t out = 0;
-        for (int k = 0; k < m && !out; ++k) {
-            const int e = sl[k];
-            const int dx = (int)(short)(e & 0xffff), dy = e >> 16;
-            const int x = tx + dx, y = ty + dy;
-            out = (x >= 0 && x < tiles_x && y >= 0 && y < tiles_y && sv[(size_t)y * tiles_x + x] == 2) ? 1 : 0;
+        const int tx = (int)(i % tiles_x);
+        const long vy = i / tiles_x;
+        const int y = (int)(vy % H), v = (int)(vy / H);
+        const uint8_t s = state[((size_t)v * tiles_y + y / kTile) * tiles_x + tx];
+        if (s == 2) continue;
+        uint8_t* row = M + ((size_t)v * H + y) * W;
+        const int x0 = tx * kTile, x1 = min(x0 + kTile, W);
+        if (x1 - x0 == kTile && (reinterpret_cast<uintptr_t>(row + x0) & 15) == 0) {
+            const uint32_t w = s ? 0x01010101u : 0u;
+            *reinterpret_cast<uint4*>(row + x0) = make_uint4(w, w, w, w);
+        } else {
+            for (int x = x0; x < x1; ++x) row[x] = s;
         }
-        near[i] = out;
     }
 }
 
@@ -410,36 +353,18 @@ hipError_t launch_edges_out(hipStream_t st, const float* D, int H, int W, float*
     return hipGetLastError();
 }
 
-int route_stencil_cap(const int* h, int n_views) {
-    int hmax = 0;
-    for (int v = 0; v < n_views; ++v) hmax = h[v] > hmax ? h[v] : hmax;
-    const int R = (hmax + 16) / 16 + 1;
-    return (2 * R + 1) * (2 * R + 1);
+hipError_t launch_route_state(hipStream_t st, const float* logits, size_t n, float z_lo, float z_hi,
+                              uint8_t* tstate) {
+    hipLaunchKernelGGL(k_route_state, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, logits, (long)n, z_lo, z_hi,
+                       tstate);
+    return hipGetLastError();
 }
 
-hipError_t launch_route(hipStream_t st, const float* logits, int n_views, int tiles_y, int tiles_x,
-                        float z_lo, float z_hi, const ViewTable& vt, const int* h, uint8_t* tstate,
-                        uint8_t* tnear, int* stencil_ws) {
-    const size_t n = (size_t)n_views * tiles_y * tiles_x;
-    RouteViews rv{};
-    int hmax = 0;
-    for (int v = 0; v < n_views; ++v) {
-        rv.c[v] = vt.c[v];
-        rv.s[v] = vt.s[v];
-        rv.h[v] = h[v];
-        hmax = h[v] > hmax ? h[v] : hmax;
-    }
-    // fp32 rounding of C + c g: a few ulps of the largest coordinate
-    const double extent = 16.0 * (tiles_x > tiles_y ? tiles_x : tiles_y) + hmax;
-    const double slack = 0.5 + extent * 1.0e-6;
-    hipLaunchKernelGGL(k_route_state, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, logits, (long)n,
-                       z_lo, z_hi, tstate);
-    const int cap = route_stencil_cap(h, n_views);
-    int* count = stencil_ws;
-    int* sten = stencil_ws + OCCL_MAX_VIEWS;
-    hipLaunchKernelGGL(k_route_stencil, dim3(n_views), dim3(256), 0, st, rv, slack, cap, count, sten);
-    hipLaunchKernelGGL(k_route_near, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, tstate, n_views,
-                       tiles_y, tiles_x, cap, count, sten, tnear);
+hipError_t launch_route_apply(hipStream_t st, const uint8_t* tstate, int n_views, int H, int W, int tiles_y,
+                              int tiles_x, uint8_t* M) {
+    const size_t n = (size_t)n_views * H * tiles_x;
+    hipLaunchKernelGGL(k_route_apply, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, tstate, n_views, H, W,
+                       tiles_y, tiles_x, M);
     return hipGetLastError();
 }
 

@@ -457,8 +457,7 @@ extern "C" occl_status occl_profile_read(occl_ctx* ctx, double* ms, int64_t* lau
 // default shape for this frame).
 occl_status occl_ctx::enqueue_frame(const float* D, int H, int W, int n_views, const int* Ls,
                                     const ViewTable& vt, const Thresholds& th, uint8_t* M,
-                                    const TuneConfig* cfg, const uint8_t* tstate,
-                                    const uint8_t* tnear, const FrameWorkspace* ws) {
+                                    const TuneConfig* cfg, const FrameWorkspace* ws) {
     int maxcls = 0;
     for (int v = 0; v < n_views; ++v) maxcls = std::max(maxcls, scan_class(Ls[v] / 2, th.thin));
     TuneConfig tc = cfg ? *cfg : config_for(tune_key(false, (size_t)H * W, n_views, maxcls));
@@ -481,8 +480,6 @@ occl_status occl_ctx::enqueue_frame(const float* D, int H, int W, int n_views, c
         f.counts = (int32_t*)counts;
         f.prefix = (int32_t*)prefix;
     }
-    f.tstate = tstate;
-    f.tnear = tnear;
     hipEvent_t ev = ws ? nullptr : prof_begin(OCCL_STAGE_EDGES);
     hipError_t e = launch_edges(stream, f, n_views, vt, th.q_min);
     if (e != hipSuccess) return hip_fail(e, "edges");

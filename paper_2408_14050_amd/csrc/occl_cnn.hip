@@ -397,23 +397,22 @@ occl_status occl_ctx::enqueue_routed(const float* D, int H, int W, int n_views, 
                                      const float* logits, uint8_t* M, uint8_t* tile_state) {
     const int ty = (H + kTile - 1) / kTile, tx = (W + kTile - 1) / kTile;
     const size_t nt = (size_t)n_views * ty * tx;
-    int h[OCCL_MAX_VIEWS];
-    for (int v = 0; v < n_views; ++v) h[v] = Ls[v] / 2;
-    void *st = tile_state, *near, *sten;
+    void* st = tile_state;
     occl_status s = OCCL_OK;
     if (!st) s = ensure("tile_state", nt, &st);
-    if (s == OCCL_OK) s = ensure("tile_near", nt, &near);
-    if (s == OCCL_OK)
-        s = ensure("tile_stencil",
-                   ((size_t)OCCL_MAX_VIEWS + (size_t)n_views * route_stencil_cap(h, n_views)) * sizeof(int),
-                   &sten);
     if (s != OCCL_OK) return s;
     hipEvent_t ev = prof_begin(OCCL_STAGE_FALLBACK);
-    hipError_t e = launch_route(stream, logits, n_views, ty, tx, logit_bound(p->cnn_lo),
-                                logit_bound(p->cnn_hi), vt, h, (uint8_t*)st, (uint8_t*)near, (int*)sten);
-    if (e != hipSuccess) return hip_fail(e, "route");
-    s = enqueue_frame(D, H, W, n_views, Ls, vt, th, M, nullptr, (const uint8_t*)st, (const uint8_t*)near);
+    hipError_t e = launch_route_state(stream, logits, nt, logit_bound(p->cnn_lo), logit_bound(p->cnn_hi),
+                                      (uint8_t*)st);
+    if (e != hipSuccess) return hip_fail(e, "route states");
+    // The exact path over the whole frame, then the confident tiles' fill.
+    // Confident tiles hold no candidates in practice (they are far from any
+    // depth edge), so restricting the exact path to the uncertain tiles and
+    // their reach saves nothing; the plain kernels are the fastest form.
+    s = enqueue_frame(D, H, W, n_views, Ls, vt, th, M, nullptr);
     if (s != OCCL_OK) return s;
+    e = launch_route_apply(stream, (const uint8_t*)st, n_views, H, W, ty, tx, M);
+    if (e != hipSuccess) return hip_fail(e, "route fill");
     prof_end(OCCL_STAGE_FALLBACK, ev);
     return OCCL_OK;
 }

@@ -128,9 +128,7 @@ struct occl_ctx {
     // events and does not become the context's "most recent frame"
     occl_status enqueue_frame(const float* D, int H, int W, int n_views, const int* Ls,
                               const occl::ViewTable& vt, const occl::Thresholds& th, uint8_t* M,
-                              const occl::TuneConfig* cfg, const uint8_t* tstate = nullptr,
-                              const uint8_t* tnear = nullptr,
-                              const occl::FrameWorkspace* ws = nullptr);
+                              const occl::TuneConfig* cfg, const occl::FrameWorkspace* ws = nullptr);
     occl_status enqueue_batch(int n_frames, const occl_frame* frames, int n_views, const int* Ls_all,
                               const occl::ViewTable& vt, const occl::Thresholds& th,
                               const occl::TuneConfig* cfg);

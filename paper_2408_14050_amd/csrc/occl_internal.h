@@ -111,15 +111,6 @@ struct FrameDesc {
     int h[OCCL_MAX_VIEWS];            // half scan length floor(L/2) per view
     int vord[OCCL_MAX_VIEWS];         // views ordered by scan class (stable)
     int cls_start[kNumClasses + 1];   // number of views of class < ci in vord
-    // Tile routing (NULL on the plain exact path): per view, 16 x 16 pixel
-    // tiles aligned to (0, 0), tiles_x = ceil(W / 16) per row.
-    //   tstate[v][ty][tx]: 0 = fill 0, 1 = fill 1, 2 = exact on this tile
-    //   tnear[v][ty][tx]: 1 if a scanline from a candidate in this tile can
-    //                     sample a tile with state 2 (only such candidates
-    //                     are kept)
-    const uint8_t* tstate;
-    const uint8_t* tnear;
-    int tiles_x;
 };
 
 constexpr int kTile = 16;
@@ -209,14 +200,14 @@ hipError_t launch_fill_u32(hipStream_t st, uint32_t* p, long long n);
 
 hipError_t launch_edges_out(hipStream_t st, const float* D, int H, int W, float* E, float* A);
 
-// Tile routing from logits z [n_views][ty][tx]: state 0 if z < z_lo, 1 if
-// z > z_hi, else 2; then the reach map tnear of the state-2 tiles through a
-// per-view stencil of tile offsets.  stencil_ws: device workspace of
-// OCCL_MAX_VIEWS + n_views * route_stencil_cap(h, n_views) ints.
-int route_stencil_cap(const int* h, int n_views);
-hipError_t launch_route(hipStream_t st, const float* logits, int n_views, int tiles_y, int tiles_x,
-                        float z_lo, float z_hi, const ViewTable& vt, const int* h, uint8_t* tstate,
-                        uint8_t* tnear, int* stencil_ws);
+// Tile states from logits z (n entries): 0 if z < z_lo, 1 if z > z_hi, else
+// 2 (NaN included).
+hipError_t launch_route_state(hipStream_t st, const float* logits, size_t n, float z_lo, float z_hi,
+                              uint8_t* tstate);
+// M[v][y][x] = state of its tile wherever that state is 0 or 1.
+hipError_t launch_route_apply(hipStream_t st, const uint8_t* tstate, int n_views, int H, int W, int tiles_y,
+                              int tiles_x, uint8_t* M);
+
 
 // Forward-warping ground truth: M[v][y][x] = 1 iff some pixel lands on the
 // same nearest target pixel of view v with a disparity larger by more than

@@ -111,7 +111,7 @@ extern "C" occl_status occl_detect_noalloc(occl_ctx* ctx, const float* D, int32_
                       reinterpret_cast<int32_t*>(base + kOffPrefix)};
     e = launch_fill_u32(ctx->stream, reinterpret_cast<uint32_t*>(ws.counts), (long long)kCountsInts);
     if (e != hipSuccess) return ctx->hip_fail(e, "clear scratch counters");
-    s = ctx->enqueue_frame(D, H, W, n_views, Ls, vt, th, M, &tc, nullptr, nullptr, &ws);
+    s = ctx->enqueue_frame(D, H, W, n_views, Ls, vt, th, M, &tc, &ws);
     if (s != OCCL_OK) return s;
     if (params->flags & OCCL_FLAG_SYNC) {
         e = hipStreamSynchronize(ctx->stream);
