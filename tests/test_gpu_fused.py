@@ -163,3 +163,27 @@ def test_two_pass_form_on_the_c3_batch(torch, ref):
         ctx.occl_release()
     for i, (M, R) in enumerate(zip(Mt, _oracle(ref, frames))):
         assert np.array_equal(M, R), f"frame {i}"
+
+
+def test_default_form_follows_the_tile_count(torch, ref):
+    """Without a tuned bucket a batch takes the fused pass from 8 tiles per
+    resident block (4,096 tiles on 256 CUs): one 1280x960 frame (300 tiles)
+    keeps the two passes, 16 frames of the mixed batch (5,642 tiles) go
+    fused; both bit-exact."""
+    from paper_2408_14050_amd import occl
+    cases = [([scenes.make_scene("c1", 1002)], "two-pass"), (scenes.make_batch(seed=3000, n_frames=16), "fused")]
+    for frames, form in cases:
+        print(f"default form: {len(frames)} frames, expect {form}", flush=True)
+        ctx = occl.Context(0)
+        try:
+            Ds = [torch.from_numpy(np.ascontiguousarray(f.D)).cuda() for f in frames]
+            Ms = [torch.full((f.n_views, f.H, f.W), 7, dtype=torch.uint8, device="cuda") for f in frames]
+            batch = [(D, M, f.scan_len) for D, M, f in zip(Ds, Ms, frames)]
+            ctx.occl_detect_batched(batch, frames[0].angles, frames[0].ratios, occl.params(**frames[0].params))
+            torch.cuda.synchronize()
+            assert ctx.occl_time_batched(1)["form"] == form
+            Mg = [M.cpu().numpy() for M in Ms]
+        finally:
+            ctx.occl_release()
+        for i, (M, R) in enumerate(zip(Mg, _oracle(ref, frames))):
+            assert np.array_equal(M, R), f"{form} frame {i}"
