@@ -130,6 +130,7 @@ occl_ctx::~occl_ctx() {
 }
 
 void occl_ctx::free_all() {
+    table_cached_dev = nullptr;
     for (auto& b : bufs) {
         if (b.second.ptr) (void)hipFree(b.second.ptr);
     }
@@ -155,6 +156,7 @@ occl_status occl_ctx::ensure(const char* name, size_t bytes, void** out) {
         drop_graphs();
     }
     size_t alloc = bytes < 256 ? 256 : bytes;
+    table_cached_dev = nullptr;  // a new buffer may reuse a freed one's address
     hipError_t e = hipMalloc(&b.ptr, alloc);
     if (e != hipSuccess) {
         b.ptr = nullptr;

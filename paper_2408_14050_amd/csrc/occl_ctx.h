@@ -53,6 +53,12 @@ struct occl_ctx {
     // batched path: frame table staging, graph cache, capture stream
     occl::FrameDesc* table_host = nullptr;  // pinned, kMaxBatch entries
     hipEvent_t table_event = nullptr;       // last upload from table_host
+    std::vector<occl::FrameDesc> table_build;  // the table being built (zeroed entries)
+    std::vector<uint8_t> table_cached;      // bytes of the last upload ...
+    const void* table_cached_dev = nullptr; // ... and its device buffer (NULL: none known)
+    // Uploads table_build[0 .. n) to dev on the stream unless the last upload
+    // put the same bytes into the same buffer.
+    occl_status upload_table(int n, void* dev);
     hipStream_t cap_stream = nullptr;       // graphs are captured here (never the null stream)
     hipStream_t cap_extra[occl::kMaxBatchBranches - 1] = {};  // further branches of a batch graph (capture only)
     hipEvent_t cap_fork = nullptr;                       // the batch graph's fork ...

@@ -187,3 +187,43 @@ def test_default_form_follows_the_tile_count(torch, ref):
             ctx.occl_release()
         for i, (M, R) in enumerate(zip(Mg, _oracle(ref, frames))):
             assert np.array_equal(M, R), f"{form} frame {i}"
+
+
+def test_alternating_batches_keep_their_own_frame_table(torch, ref):
+    """A repeated batch skips its frame-table upload; alternating two batches
+    of different frames (and buffers) on one context, and then the first
+    again with new contents in the same buffers, each result is still the
+    oracle's."""
+    from paper_2408_14050_amd import occl
+    fa = scenes.make_batch(seed=3001, n_frames=16)
+    fb = [scenes.make_scene("c1", 1003)] * 2
+    fa2 = [scenes.Scene(f.name, f.seed, np.ascontiguousarray(f.D[:, ::-1]), f.angles, f.ratios, f.scan_len,
+                        dict(f.params)) for f in fa]  # same shapes, mirrored contents
+    print("alternating batches", flush=True)
+    ctx = occl.Context(0)
+    try:
+        def put(frames):
+            Ds = [torch.from_numpy(np.ascontiguousarray(f.D)).cuda() for f in frames]
+            Ms = [torch.full((f.n_views, f.H, f.W), 7, dtype=torch.uint8, device="cuda") for f in frames]
+            return Ds, Ms
+        Da, Ma = put(fa)
+        Db, Mb = put(fb)
+        prm = occl.params(**fa[0].params)
+        outs = []
+        for frames, Ds, Ms in ((fa, Da, Ma), (fb, Db, Mb), (fa, Da, Ma)):
+            batch = [(D, M, f.scan_len) for D, M, f in zip(Ds, Ms, frames)]
+            ctx.occl_detect_batched(batch, frames[0].angles, frames[0].ratios, prm)
+            torch.cuda.synchronize()
+            outs.append((frames, [M.cpu().numpy() for M in Ms]))
+        # same buffers and shapes, new contents: the table is the same, the masks are not
+        for D, f in zip(Da, fa2):
+            D.copy_(torch.from_numpy(f.D))
+        batch = [(D, M, f.scan_len) for D, M, f in zip(Da, Ma, fa2)]
+        ctx.occl_detect_batched(batch, fa2[0].angles, fa2[0].ratios, prm)
+        torch.cuda.synchronize()
+        outs.append((fa2, [M.cpu().numpy() for M in Ma]))
+    finally:
+        ctx.occl_release()
+    for frames, Ms in outs:
+        for i, (M, R) in enumerate(zip(Ms, _oracle(ref, frames))):
+            assert np.array_equal(M, R), f"frame {i}"
