@@ -227,3 +227,29 @@ def test_alternating_batches_keep_their_own_frame_table(torch, ref):
     for frames, Ms in outs:
         for i, (M, R) in enumerate(zip(Ms, _oracle(ref, frames))):
             assert np.array_equal(M, R), f"frame {i}"
+
+
+@pytest.mark.parametrize("n_views", [1, 64])
+def test_fused_one_and_the_most_views(torch, ref, n_views):
+    """The fused pass with one view and with its maximum of 64 (a round then
+    holds 64 strong pixels; the view index takes the entry's top bits):
+    random angles, ratios in [1, 2.83], L from 1 to 127 per view and frame."""
+    from paper_2408_14050_amd import occl
+    rng = np.random.default_rng(900 + n_views)
+    sizes = [(256, 160), (300, 97), (517, 40)]
+    frames = [scenes.make_c1_like(int(rng.integers(0, 1 << 30)), W=w, H=h, n_objects=6) for w, h in sizes]
+    angles = rng.uniform(0.0, 360.0, n_views)
+    ratios = rng.uniform(1.0, 2.83, n_views).astype(np.float32)
+    for f in frames:
+        f.angles, f.ratios = angles, ratios
+        f.scan_len = rng.integers(1, 128, n_views).astype(np.int32)
+    print(f"fused {n_views} views", flush=True)
+    ctx = occl.Context(0)
+    try:
+        Mf, _, _ = _run(ctx, torch, frames, 0)
+        assert ctx.occl_time_batched(1)["form"] == "fused"
+    finally:
+        ctx.occl_release()
+    for i, (M, f) in enumerate(zip(Mf, frames)):
+        R = ref.detect(f.D, f.angles, f.ratios, f.scan_len, **f.params)[0]
+        assert np.array_equal(M, R), f"frame {i} {f.W}x{f.H}: {int((M != R).sum())} bytes differ"
