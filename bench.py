@@ -179,8 +179,9 @@ def cpu_baseline(frames, seconds: float, max_threads: int = 16):
 
 
 def bitonic_ops(n_cand, scan_len, neighbours=1):
-    """Algorithmic ALU work of Eqs. (4)-(6) as the survey counts it: per
-    scanline of n samples a bitonic sort of n' = 2^ceil(log2 n) keys,
+    """Algorithmic ALU work of Eqs. (4)-(6), counted as a sorting network
+    would do it: per scanline of n samples a bitonic sort of
+    n' = 2^ceil(log2 n) keys,
     (n'/2) log2 n' (log2 n' + 1) / 2 compare-exchanges, plus 2 n_s n
     neighbour tests."""
     ns = max(1, (neighbours + 1) // 2)
