@@ -8,11 +8,10 @@
 // Output size of a stride-s layer: ceil(H / s).
 //
 // The 32-output-channel layers are implicit GEMMs on MFMA: one wavefront
-// computes 32 output pixels x 32 channels.  Operand layout of
-// v_mfma_f32_32x32x8_bf16 (checked on the device): lane l supplies
-// A[l % 32][4*(l/32) + i] and B[4*(l/32) + i][l % 32], i = 0..3, and
-// accumulator register j of lane l holds D[8*(j/4) + 4*(l/32) + (j%4)][l % 32];
-// the 32x32x16 form takes 8 consecutive K per lane half the same way.
+// computes 32 output pixels x 32 channels on v_mfma_f32_32x32x16_bf16
+// (operand layout checked on the device): lane l supplies
+// A[l % 32][8*(l/32) + i] and B[8*(l/32) + i][l % 32], i = 0..7, and
+// accumulator register j of lane l holds D[8*(j/4) + 4*(l/32) + (j%4)][l % 32].
 //   forward  M = output pixels, N = output channels, K = 9 * Cin (32x32x16;
 //            weights resident in registers, persistent wavefronts)
 //   dgrad    M = input pixels,  N = input channels,  K = 9 * Cout (weights
@@ -29,14 +28,11 @@
 namespace occl {
 namespace {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef short s16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// D += A B on v_mfma_f32_32x32x16_bf16: lane l supplies A[l % 32][8*(l/32) + i]
-// and B[8*(l/32) + i][l % 32], i = 0..7 (the accumulator layout is that of
-// the 32x32x8 form)
+// D += A B on v_mfma_f32_32x32x16_bf16 (lane layout in the header comment)
 __device__ __forceinline__ f32x16 mfma16(s16x8 a, s16x8 b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
@@ -74,10 +70,6 @@ __device__ __forceinline__ void load_bias16(const float* __restrict__ b, int q, 
     for (int g = 0; g < 4; ++g)
 #pragma unroll
         for (int i = 0; i < 4; ++i) out[4 * g + i] = b[8 * g + 4 * q + i];
-}
-
-__device__ __forceinline__ bf16x4 load4(const uint16_t* p) {
-    return *reinterpret_cast<const bf16x4*>(p);
 }
 
 // ---------------------------------------------------------------------------
@@ -506,11 +498,11 @@ __global__ __launch_bounds__(320) void k_wgrad_last(const float* __restrict__ dZ
 // ---------------------------------------------------------------------------
 // backward of a 32-output-channel layer with ReLU: g = dY * [Y > 0]
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bf16x4 relu_grad4(const uint16_t* dy, const uint16_t* y) {
-    const bf16x4 g = load4(dy), a = load4(y);
-    bf16x4 o;
+__device__ __forceinline__ s16x8 relu_grad8(const uint16_t* dy, const uint16_t* y) {
+    const s16x8 g = *reinterpret_cast<const s16x8*>(dy), a = *reinterpret_cast<const s16x8*>(y);
+    s16x8 o;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) o[i] = (bf2f((uint16_t)a[i]) > 0.0f) ? g[i] : (short)0;
+    for (int i = 0; i < 8; ++i) o[i] = (bf2f((uint16_t)a[i]) > 0.0f) ? g[i] : (short)0;
     return o;
 }
 
@@ -541,11 +533,11 @@ __global__ __launch_bounds__(256) void k_conv_dgrad(const uint16_t* __restrict__
         const size_t o = (((size_t)n * Ho + (ok ? oy : 0)) * Wo + (ok ? ox : 0)) * 32;
         const uint16_t* wrow = WT + ((size_t)t * 32 + i32) * 32;
 #pragma unroll
-        for (int cc = 0; cc < 4; ++cc) {
-            const bf16x4 a = ok ? relu_grad4(dY + o + 8 * cc + 4 * q, Y + o + 8 * cc + 4 * q)
-                                : bf16x4{0, 0, 0, 0};
-            const bf16x4 b = load4(wrow + 8 * cc + 4 * q);
-            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+        for (int cc = 0; cc < 2; ++cc) {  // output channels 16 cc .. 16 cc + 15 (8 per lane half)
+            const s16x8 a = ok ? relu_grad8(dY + o + 16 * cc + 8 * q, Y + o + 16 * cc + 8 * q)
+                               : s16x8{0, 0, 0, 0, 0, 0, 0, 0};
+            const s16x8 b = *reinterpret_cast<const s16x8*>(wrow + 16 * cc + 8 * q);
+            acc = mfma16(a, b, acc);
         }
     }
 #pragma unroll
@@ -573,11 +565,11 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(const uint16_t* __restrict__ 
     const bool cvalid = col < NCOL;
     const int t = cvalid ? col / CIN : 0, ci = cvalid ? col % CIN : 0;
     f32x16 acc = {};
-    for (int k0 = 0; k0 < chunk; k0 += 8) {
-        bf16x4 a, b;
+    for (int k0 = 0; k0 < chunk; k0 += 16) {  // 16 pixels per step, 8 per lane half
+        s16x8 a, b;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const long p = p0 + k0 + 4 * q + i;
+        for (int i = 0; i < 8; ++i) {
+            const long p = p0 + k0 + 8 * q + i;
             short av = 0, bv = 0;
             if (p < total && p < p0 + chunk) {
                 const size_t o = (size_t)p * 32 + i32;  // A[co = i32][k = p]
@@ -593,7 +585,7 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(const uint16_t* __restrict__ 
             a[i] = av;
             b[i] = bv;
         }
-        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+        acc = mfma16(a, b, acc);
     }
     float* out = partial + (size_t)blockIdx.x * 32 * NCOL;
 #pragma unroll
