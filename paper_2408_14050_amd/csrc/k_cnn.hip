@@ -32,6 +32,9 @@ typedef short s16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
+// Pixels per weight-gradient partial (one block of k_conv_wgrad / k_bias_grad).
+constexpr int kWgradChunk = 512;
+
 // D += A B on v_mfma_f32_32x32x16_bf16 (lane layout in the header comment)
 __device__ __forceinline__ f32x16 mfma16(s16x8 a, s16x8 b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
@@ -619,14 +622,40 @@ __global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ 
 }
 
 // out[k] = sum over chunks c (in order) of partial[c][k]
+// Chunk partials partial[c][k] (c < n_chunks, k < n_out) are summed in a
+// fixed order, so a gradient does not depend on the launch: with more than
+// kReduceGroup chunks, first the chunks of each group of kReduceGroup in
+// order, the sum written in place over the group's first chunk (block
+// (x, g): group g), then those group sums in order.
+constexpr int kReduceGroup = 64;
+__global__ __launch_bounds__(256) void k_reduce_groups(float* __restrict__ partial, int n_chunks, int n_out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_out) return;
+    const int c0 = (int)blockIdx.y * kReduceGroup;
+    const int c1 = c0 + kReduceGroup < n_chunks ? c0 + kReduceGroup : n_chunks;
+    float s = 0.0f;
+    for (int c = c0; c < c1; ++c) s += partial[(size_t)c * n_out + k];
+    partial[(size_t)c0 * n_out + k] = s;
+}
+
+// out[k] = sum of partial[c][k] over c = 0, step, 2 step, ... < n_chunks, in order
 __global__ __launch_bounds__(256) void k_reduce_chunks(const float* __restrict__ partial,
                                                        float* __restrict__ out, int n_chunks,
-                                                       int n_out) {
+                                                       int n_out, int step) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_out) return;
     float s = 0.0f;
-    for (int c = 0; c < n_chunks; ++c) s += partial[(size_t)c * n_out + k];
+    for (int c = 0; c < n_chunks; c += step) s += partial[(size_t)c * n_out + k];
     out[k] = s;
+}
+
+void reduce_chunks(hipStream_t st, float* partial, float* out, int n_chunks, int n_out) {
+    const int groups = (n_chunks + kReduceGroup - 1) / kReduceGroup;
+    if (groups > 1)
+        hipLaunchKernelGGL(k_reduce_groups, dim3((n_out + 255) / 256, groups), dim3(256), 0, st, partial, n_chunks,
+                           n_out);
+    hipLaunchKernelGGL(k_reduce_chunks, dim3((n_out + 255) / 256), dim3(256), 0, st, partial, out, n_chunks, n_out,
+                       groups > 1 ? kReduceGroup : 1);
 }
 
 // WT[tap][ci][co] = W[co][tap][ci] (bf16) for the dgrad of a 32x32 layer
@@ -781,15 +810,14 @@ hipError_t cnn_last_backward(hipStream_t st, const float* dZ, const uint16_t* X,
     const int chunk = 256;
     const int n_chunks = (int)((total + chunk - 1) / chunk);
     hipLaunchKernelGGL(k_wgrad_last, dim3(n_chunks), dim3(320), 0, st, dZ, X, partial, N, H, W, chunk);
-    hipLaunchKernelGGL(k_reduce_chunks, dim3((289 + 255) / 256), dim3(256), 0, st, partial, gw_out,
-                       n_chunks, 289);
+    reduce_chunks(st, partial, gw_out, n_chunks, 289);
     hipLaunchKernelGGL(k_dgrad_last, dim3(blocks_for(total * 32, 256, 65535)), dim3(256), 0, st, dZ, Wt,
                        dX, N, H, W);
     return hipGetLastError();
 }
 
 size_t cnn_wgrad_partial_floats(long pixels, int cin) {
-    const int chunk = 512;
+    const int chunk = kWgradChunk;
     const long n_chunks = (pixels + chunk - 1) / chunk;
     return (size_t)n_chunks * 32 * 9 * cin + (size_t)n_chunks * 32;
 }
@@ -800,7 +828,7 @@ hipError_t cnn_layer_backward(hipStream_t st, int cin, int stride, const uint16_
                               uint16_t* WT, uint16_t* dX, float* partial, float* gw_out, int N, int H,
                               int W, int Ho, int Wo) {
     const long total = (long)N * Ho * Wo;
-    const int chunk = 512;
+    const int chunk = kWgradChunk;
     const int n_chunks = (int)((total + chunk - 1) / chunk);
     const int ncol = 9 * cin;
     const dim3 wg(n_chunks, (ncol + 31) / 32);
@@ -812,11 +840,10 @@ hipError_t cnn_layer_backward(hipStream_t st, int cin, int stride, const uint16_
         hipLaunchKernelGGL((k_conv_wgrad<32, 1>), wg, dim3(64), 0, st, dY, Y, X, partial, N, H, W, Ho, Wo, chunk);
     else
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_reduce_chunks, dim3((32 * ncol + 255) / 256), dim3(256), 0, st, partial, gw_out,
-                       n_chunks, 32 * ncol);
+    reduce_chunks(st, partial, gw_out, n_chunks, 32 * ncol);
     float* bpart = partial + (size_t)n_chunks * 32 * ncol;
     hipLaunchKernelGGL(k_bias_grad, dim3(n_chunks), dim3(256), 0, st, dY, Y, bpart, total, chunk);
-    hipLaunchKernelGGL(k_reduce_chunks, dim3(1), dim3(256), 0, st, bpart, gw_out + 32 * ncol, n_chunks, 32);
+    reduce_chunks(st, bpart, gw_out + 32 * ncol, n_chunks, 32);
     if (dX) {  // input gradient (not needed for the first layer)
         if (cin != 32) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_transpose_w, dim3((32 * 9 * 32 + 255) / 256), dim3(256), 0, st, Wt, WT);
