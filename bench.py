@@ -41,7 +41,8 @@ CSRC = "paper_2408_14050_amd/csrc/"
 
 
 def kernel_source(kernel: str) -> str:
-    if kernel.startswith(("k_conv", "k_pack", "k_bce", "k_adam", "k_wgrad", "k_dgrad")):
+    if kernel.startswith(("k_conv", "k_pack", "k_bce", "k_adam", "k_wgrad", "k_dgrad", "k_reduce", "k_bias_grad",
+                          "k_transpose_w")):
         return CSRC + "k_cnn.hip"
     if kernel.startswith(("k_route", "k_stats", "k_confusion", "k_zbuf", "k_fill", "k_median",
                           "k_edges_out")):
@@ -203,7 +204,13 @@ QUALITY_PROFILE_CMD = ("rocprofv3 {mode} -d gpurun_out/{out} -o run -- python3 b
                        "--quality-only")
 THIN_PROFILE_CMD = "rocprofv3 {mode} -d gpurun_out/{out} -o run -- python3 bench.py --thin-only"
 LEARNED_PROFILE_CMD = ("rocprofv3 {mode} -d gpurun_out/{out} -o run -- python3 bench.py --learned-only "
-                       "--learned-steps 10 --learned-eval 1")
+                       "--learned-steps 10 --learned-eval 1 --no-train-step")
+TRAIN_PROFILE_CMD = ("rocprofv3 {mode} -d gpurun_out/{out} -o run -- python3 bench.py --train-only "
+                     "--train-steps 10")
+TRAIN_WORKLOAD = "training step 128 crops 256x256 x8 channels"
+TRAIN_KERNELS = ("k_conv_fwd_p", "k_conv_last", "k_conv_wgrad", "k_conv_dgrad", "k_reduce_groups",
+                 "k_reduce_chunks", "k_bias_grad", "k_wgrad_last", "k_dgrad_last", "k_adam", "k_bce",
+                 "k_transpose_w")
 BATCH_WORKLOAD = "c3 64 mixed frames seed 3000"
 C1_WORKLOAD = "c1 1280x960 x8 views seed 1002"
 C2_WORKLOAD = "c2 3840x2160 x15 views seed 2000"
@@ -271,7 +278,8 @@ def profiles_from(run_dir: str, workload: str) -> int:
     """Writes profiles/<kernel>__<workload>.txt and profiles/traffic.json from
     the rocprofv3 databases of the profiling runs: trace, FETCH_SIZE and
     WRITE_SIZE passes of the benchmark (prof, pmc_fetch, pmc_write), of its
-    learned, quality and thinning sections (l-, q- and t-prefixed; optional)
+    learned, quality, thinning, c2 and training sections (l-, q-, t-, c- and
+    r-prefixed; optional)
     and of the copy probe (copy_fetch, copy_write)."""
     import glob
     def db(sub):
@@ -296,7 +304,8 @@ def profiles_from(run_dir: str, workload: str) -> int:
             ("l", LEARNED_PROFILE_CMD, lambda k: k.startswith(LEARNED_KERNELS)),
             ("q", QUALITY_PROFILE_CMD, lambda k: k.startswith(QUALITY_KERNELS)),
             ("t", THIN_PROFILE_CMD, lambda k: k.startswith(THIN_KERNELS)),
-            ("c", C2_PROFILE_CMD, lambda k: k.startswith(C2_KERNELS))]
+            ("c", C2_PROFILE_CMD, lambda k: k.startswith(C2_KERNELS)),
+            ("r", TRAIN_PROFILE_CMD, lambda k: k.startswith(TRAIN_KERNELS))]
     for pre, cmd, keep in runs:
         if not db(pre + "prof"):
             continue
@@ -312,6 +321,8 @@ def profiles_from(run_dir: str, workload: str) -> int:
                 wl = THIN_WORKLOAD
             elif pre == "c":
                 wl = C2_WORKLOAD
+            elif pre == "r":
+                wl = TRAIN_WORKLOAD
             else:
                 wl = BATCH_WORKLOAD if any(x in k for x in ("batched", "finish_frames", "k_fused",
                                                            "k_clear_masks")) else workload
@@ -727,7 +738,50 @@ def cnn_flops(H: int, W: int) -> int:
     return tot
 
 
-def bench_learned(ctx, steps: int, n_eval: int):
+def cnn_train_flops(H: int, W: int) -> int:
+    """Multiply-adds x 2 of one training step of the tile network on one
+    H x W input: the forward, the weight gradient of every layer and the
+    input gradient of every layer but the first."""
+    layers = [(8, 32, 2), (32, 32, 2), (32, 32, 2), (32, 32, 2), (32, 32, 1), (32, 1, 1)]
+    tot = 0
+    for li, (ci, co, st) in enumerate(layers):
+        H, W = (H + st - 1) // st, (W + st - 1) // st
+        f = 2 * H * W * co * 9 * ci
+        tot += f * (3 if li > 0 else 2)
+    return tot
+
+
+def bench_train(steps: int, crops: int = 128, crop: int = 256):
+    """One Adam step of the tile network on `crops` random crops of crop x
+    crop x 8 input channels (the training batch of the shipped weights), on a
+    context of its own: ms per step, crops/s and the convolutions' TFLOP/s."""
+    import numpy as np
+    import torch
+    from paper_2408_14050_amd import occl
+    tctx = occl.Context(0)
+    tctx.occl_cnn_init(1)
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal(size=(crops, crop, crop, 8), dtype=np.float32)
+    x[..., 7] = 0.0
+    X = torch.from_numpy((x.view(np.uint32) >> 16).astype(np.uint16).view(np.int16)).cuda()
+    del x
+    T = torch.from_numpy(rng.uniform(size=(crops, crop // 16, crop // 16)).astype(np.float32)).cuda()
+    for _ in range(3):
+        tctx.occl_cnn_train_step(X, T, 1e-3, want_loss=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        tctx.occl_cnn_train_step(X, T, 1e-3, want_loss=False)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    tctx.occl_release()
+    fl = cnn_train_flops(crop, crop) * crops
+    return {"workload": f"{crops} random crops of {crop}x{crop} x 8 channels, one Adam step each",
+            "steps": steps, "ms_per_step": round(dt * 1e3, 4), "crops_per_s": round(crops / dt, 1),
+            "gflop_per_step": round(fl / 1e9, 2), "tflops": round(fl / dt / 1e12, 2)}
+
+
+def bench_learned(ctx, steps: int, n_eval: int, train: bool = True):
     """Learned tile proposal + exact fallback against the exact path on
     1920x1080 frames x 8 views (c1 statistics, held-out seeds 4100...)."""
     import torch
@@ -778,6 +832,7 @@ def bench_learned(ctx, steps: int, n_eval: int):
     out = {"workload": "c4: 1920x1080 x8 views, c1 statistics, held-out seeds "
                        f"{EVAL_SEED0}..{EVAL_SEED0 + len(frames) - 1} (timing on the first)",
            "weights": os.path.relpath(DEFAULT_WEIGHTS, ROOT), "training": meta,
+           "train_step": bench_train(max(5, steps // 2)) if train else None,
            "exact": {"ms": round(dt_exact * 1e3, 4), "mpixel_views_per_s": round(pv / dt_exact / 1e6, 1),
                      "stages_ms": st_exact}}
     fl = cnn_flops(sc.H, sc.W) * 8
@@ -818,6 +873,9 @@ def main() -> int:
     ap.add_argument("--profiles-from", default=None, metavar="DIR")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-only", action="store_true", help="only the learned-path section")
+    ap.add_argument("--train-only", action="store_true", help="only the network's training step")
+    ap.add_argument("--train-steps", type=int, default=20)
+    ap.add_argument("--no-train-step", action="store_true", help="learned section without the training step")
     ap.add_argument("--no-quality", action="store_true")
     ap.add_argument("--quality-only", action="store_true", help="only the quality and fusion sections")
     ap.add_argument("--thin-only", action="store_true", help="only the candidate-thinning section")
@@ -844,9 +902,13 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
         return 3
+    if args.train_only:
+        print(json.dumps({"train_step": bench_train(args.train_steps)}), flush=True)
+        return 0
     if args.learned_only:
         ctx = occl.Context(0)
-        print(json.dumps(bench_learned(ctx, args.learned_steps, args.learned_eval)), flush=True)
+        print(json.dumps(bench_learned(ctx, args.learned_steps, args.learned_eval, not args.no_train_step)),
+              flush=True)
         ctx.occl_release()
         return 0
     if args.thin_only:
@@ -925,7 +987,7 @@ def main() -> int:
             "paper_hw": "NVIDIA GeForce RTX 3090 (paper's own scene, not this one)"}
 
     if not args.no_learned:
-        out["learned"] = bench_learned(ctx, args.learned_steps, args.learned_eval)
+        out["learned"] = bench_learned(ctx, args.learned_steps, args.learned_eval, not args.no_train_step)
         ex = out["learned"]["exact"]
         pv4 = 1920 * 1080 * 8
         out["c4_exact"] = {"workload": "c4 1920x1080 x8 views, c1 statistics, seed 4100",
