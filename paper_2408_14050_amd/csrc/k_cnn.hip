@@ -32,7 +32,7 @@ typedef short s16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// Pixels per weight-gradient partial (one block of k_conv_wgrad / k_bias_grad).
+// Pixels per weight-gradient partial (one block of k_conv_wgrad).
 constexpr int kWgradChunk = 512;
 
 // D += A B on v_mfma_f32_32x32x16_bf16 (lane layout in the header comment)
@@ -552,13 +552,16 @@ __global__ __launch_bounds__(256) void k_conv_dgrad(const uint16_t* __restrict__
 
 // wgrad partials of a 32-output-channel layer: block (chunk, tile) computes
 // the 32 x 32 tile of columns [32*tile, 32*tile + 32) of dW[co][t*CIN + ci]
-// over the chunk's pixels; partial layout [chunk][32][9*CIN].
+// over the chunk's pixels; partial layout [chunk][32][9*CIN].  The blocks of
+// tile 0 also sum g = dY [Y > 0] over the chunk's pixels per channel: the
+// bias gradient's partials, bpartial [chunk][32] (each lane half sums its
+// pixels in order, then the two halves are added).
 template <int CIN, int S>
 __global__ __launch_bounds__(64) void k_conv_wgrad(const uint16_t* __restrict__ dY,
                                                    const uint16_t* __restrict__ Y,
                                                    const uint16_t* __restrict__ X,
-                                                   float* __restrict__ partial, int N, int H, int W,
-                                                   int Ho, int Wo, int chunk) {
+                                                   float* __restrict__ partial, float* __restrict__ bpartial,
+                                                   int N, int H, int W, int Ho, int Wo, int chunk) {
     constexpr int NCOL = 9 * CIN;
     const int lane = threadIdx.x;
     const int q = lane >> 5, i32 = lane & 31;
@@ -567,28 +570,49 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(const uint16_t* __restrict__ 
     const int col = blockIdx.y * 32 + i32;  // B column of this lane
     const bool cvalid = col < NCOL;
     const int t = cvalid ? col / CIN : 0, ci = cvalid ? col % CIN : 0;
+    const long hwo = (long)Ho * Wo;
+    const int dy = t / 3 - 1, dx = t % 3 - 1;
+    const bool bias = blockIdx.y == 0;  // uniform
+    float bsum = 0.0f;
     f32x16 acc = {};
     for (int k0 = 0; k0 < chunk; k0 += 16) {  // 16 pixels per step, 8 per lane half
+        // this lane's 8 consecutive pixels: the first one's (n, oy, ox) by
+        // division, the others by stepping along the row
+        const long pb = p0 + k0 + 8 * q;
+        const long pc = pb < total ? pb : 0;
+        int n = (int)(pc / hwo);
+        const int rem = (int)(pc - (long)n * hwo);
+        int oy = rem / Wo, ox = rem - oy * Wo;
         s16x8 a, b;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            const long p = p0 + k0 + 8 * q + i;
+            const long p = pb + i;
             short av = 0, bv = 0;
             if (p < total && p < p0 + chunk) {
                 const size_t o = (size_t)p * 32 + i32;  // A[co = i32][k = p]
                 av = (bf2f(Y[o]) > 0.0f) ? (short)dY[o] : (short)0;
+                if (bias) bsum += bf2f((uint16_t)av);
                 if (cvalid) {
-                    const int n = (int)(p / ((long)Ho * Wo));
-                    const int rem = (int)(p % ((long)Ho * Wo));
-                    const int iy = (rem / Wo) * S + t / 3 - 1, ix = (rem % Wo) * S + t % 3 - 1;
+                    const int iy = oy * S + dy, ix = ox * S + dx;
                     if (iy >= 0 && iy < H && ix >= 0 && ix < W)
                         bv = (short)X[(((size_t)n * H + iy) * W + ix) * CIN + ci];
                 }
             }
             a[i] = av;
             b[i] = bv;
+            if (++ox == Wo) {
+                ox = 0;
+                if (++oy == Ho) {
+                    oy = 0;
+                    ++n;
+                }
+            }
         }
         acc = mfma16(a, b, acc);
+    }
+    if (bias) {
+        const float other = __shfl_xor(bsum, 32);
+        if (q == 0) bpartial[(size_t)blockIdx.x * 32 + i32] = bsum + other;
     }
     float* out = partial + (size_t)blockIdx.x * 32 * NCOL;
 #pragma unroll
@@ -598,30 +622,6 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(const uint16_t* __restrict__ 
     }
 }
 
-// bias gradient partials of a 32-channel layer with ReLU: [chunk][32]
-__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ dY,
-                                                   const uint16_t* __restrict__ Y,
-                                                   float* __restrict__ partial, long total,
-                                                   int chunk) {
-    __shared__ float red[8][32];
-    const int co = threadIdx.x & 31, part = threadIdx.x >> 5;
-    const long p0 = (long)blockIdx.x * chunk;
-    const long p1 = p0 + chunk < total ? p0 + chunk : total;
-    float acc = 0.0f;
-    for (long p = p0 + part; p < p1; p += 8) {
-        const size_t o = (size_t)p * 32 + co;
-        if (bf2f(Y[o]) > 0.0f) acc += bf2f(dY[o]);
-    }
-    red[part][co] = acc;
-    __syncthreads();
-    if (part == 0) {
-        float s = 0.0f;
-        for (int k = 0; k < 8; ++k) s += red[k][co];
-        partial[(size_t)blockIdx.x * 32 + co] = s;
-    }
-}
-
-// out[k] = sum over chunks c (in order) of partial[c][k]
 // Chunk partials partial[c][k] (c < n_chunks, k < n_out) are summed in a
 // fixed order, so a gradient does not depend on the launch: with more than
 // kReduceGroup chunks, first the chunks of each group of kReduceGroup in
@@ -832,17 +832,19 @@ hipError_t cnn_layer_backward(hipStream_t st, int cin, int stride, const uint16_
     const int n_chunks = (int)((total + chunk - 1) / chunk);
     const int ncol = 9 * cin;
     const dim3 wg(n_chunks, (ncol + 31) / 32);
+    float* bpart = partial + (size_t)n_chunks * 32 * ncol;
     if (cin == 8 && stride == 2)
-        hipLaunchKernelGGL((k_conv_wgrad<8, 2>), wg, dim3(64), 0, st, dY, Y, X, partial, N, H, W, Ho, Wo, chunk);
+        hipLaunchKernelGGL((k_conv_wgrad<8, 2>), wg, dim3(64), 0, st, dY, Y, X, partial, bpart, N, H, W, Ho, Wo,
+                           chunk);
     else if (cin == 32 && stride == 2)
-        hipLaunchKernelGGL((k_conv_wgrad<32, 2>), wg, dim3(64), 0, st, dY, Y, X, partial, N, H, W, Ho, Wo, chunk);
+        hipLaunchKernelGGL((k_conv_wgrad<32, 2>), wg, dim3(64), 0, st, dY, Y, X, partial, bpart, N, H, W, Ho, Wo,
+                           chunk);
     else if (cin == 32 && stride == 1)
-        hipLaunchKernelGGL((k_conv_wgrad<32, 1>), wg, dim3(64), 0, st, dY, Y, X, partial, N, H, W, Ho, Wo, chunk);
+        hipLaunchKernelGGL((k_conv_wgrad<32, 1>), wg, dim3(64), 0, st, dY, Y, X, partial, bpart, N, H, W, Ho, Wo,
+                           chunk);
     else
         return hipErrorInvalidValue;
     reduce_chunks(st, partial, gw_out, n_chunks, 32 * ncol);
-    float* bpart = partial + (size_t)n_chunks * 32 * ncol;
-    hipLaunchKernelGGL(k_bias_grad, dim3(n_chunks), dim3(256), 0, st, dY, Y, bpart, total, chunk);
     reduce_chunks(st, bpart, gw_out + 32 * ncol, n_chunks, 32);
     if (dX) {  // input gradient (not needed for the first layer)
         if (cin != 32) return hipErrorInvalidValue;
