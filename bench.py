@@ -41,7 +41,7 @@ CSRC = "paper_2408_14050_amd/csrc/"
 
 
 def kernel_source(kernel: str) -> str:
-    if kernel.startswith(("k_conv", "k_pack", "k_bce", "k_adam", "k_wgrad", "k_dgrad", "k_reduce", "k_bias_grad",
+    if kernel.startswith(("k_conv", "k_pack", "k_bce", "k_adam", "k_wgrad", "k_dgrad", "k_reduce",
                           "k_transpose_w")):
         return CSRC + "k_cnn.hip"
     if kernel.startswith(("k_route", "k_stats", "k_confusion", "k_zbuf", "k_fill", "k_median",
@@ -209,7 +209,7 @@ TRAIN_PROFILE_CMD = ("rocprofv3 {mode} -d gpurun_out/{out} -o run -- python3 ben
                      "--train-steps 10")
 TRAIN_WORKLOAD = "training step 128 crops 256x256 x8 channels"
 TRAIN_KERNELS = ("k_conv_fwd_p", "k_conv_last", "k_conv_wgrad", "k_conv_dgrad", "k_reduce_groups",
-                 "k_reduce_chunks", "k_bias_grad", "k_wgrad_last", "k_dgrad_last", "k_adam", "k_bce",
+                 "k_reduce_chunks", "k_wgrad_last", "k_dgrad_last", "k_adam", "k_bce",
                  "k_transpose_w")
 BATCH_WORKLOAD = "c3 64 mixed frames seed 3000"
 C1_WORKLOAD = "c1 1280x960 x8 views seed 1002"
