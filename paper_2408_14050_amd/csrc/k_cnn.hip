@@ -550,75 +550,110 @@ __global__ __launch_bounds__(256) void k_conv_dgrad(const uint16_t* __restrict__
     }
 }
 
-// wgrad partials of a 32-output-channel layer: block (chunk, tile) computes
-// the 32 x 32 tile of columns [32*tile, 32*tile + 32) of dW[co][t*CIN + ci]
-// over the chunk's pixels; partial layout [chunk][32][9*CIN].  The blocks of
-// tile 0 also sum g = dY [Y > 0] over the chunk's pixels per channel: the
-// bias gradient's partials, bpartial [chunk][32] (each lane half sums its
-// pixels in order, then the two halves are added).
+// wgrad partials of a 32-output-channel layer: block `chunk` computes every
+// 32 x 32 tile of dW[co][t*CIN + ci] (co rows, columns col = t*CIN + ci) over
+// the chunk's pixels; partial layout [chunk][32][9*CIN].  Per step of 16
+// pixels the block stages, with 16-byte loads, the relu-masked output
+// gradient g = dY [Y > 0] (gs[pixel][co]) and the input under each tap
+// (xs[pixel][col], zero outside the image) in LDS; wavefront w then runs the
+// column tiles w, w + 4, ..., taking its MFMA operands from LDS (8 pixels of
+// one row or column per lane half).  It also writes the bias gradient's
+// partials, bpartial [chunk][32]: the sum of g over the chunk's pixels, per
+// pixel slot in step order, then the 16 slots in order.
 template <int CIN, int S>
-__global__ __launch_bounds__(64) void k_conv_wgrad(const uint16_t* __restrict__ dY,
-                                                   const uint16_t* __restrict__ Y,
-                                                   const uint16_t* __restrict__ X,
-                                                   float* __restrict__ partial, float* __restrict__ bpartial,
-                                                   int N, int H, int W, int Ho, int Wo, int chunk) {
+__global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t* __restrict__ dY,
+                                                    const uint16_t* __restrict__ Y,
+                                                    const uint16_t* __restrict__ X,
+                                                    float* __restrict__ partial, float* __restrict__ bpartial,
+                                                    int N, int H, int W, int Ho, int Wo, int chunk) {
     constexpr int NCOL = 9 * CIN;
-    const int lane = threadIdx.x;
+    constexpr int NT = (NCOL + 31) / 32;  // column tiles
+    constexpr int NCP = NT * 32;          // columns, padded to whole tiles
+    constexpr int TPW = (NT + 3) / 4;     // tiles per wavefront
+    constexpr int XV = CIN / 8;           // 16-byte vectors of X per pixel
+    __shared__ __align__(16) uint16_t gs[16][32];
+    __shared__ __align__(16) uint16_t xs[16][NCP];
+    __shared__ float bred[64][8];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int q = lane >> 5, i32 = lane & 31;
     const long total = (long)N * Ho * Wo;
     const long p0 = (long)blockIdx.x * chunk;
-    const int col = blockIdx.y * 32 + i32;  // B column of this lane
-    const bool cvalid = col < NCOL;
-    const int t = cvalid ? col / CIN : 0, ci = cvalid ? col % CIN : 0;
     const long hwo = (long)Ho * Wo;
-    const int dy = t / 3 - 1, dx = t % 3 - 1;
-    const bool bias = blockIdx.y == 0;  // uniform
-    float bsum = 0.0f;
-    f32x16 acc = {};
-    for (int k0 = 0; k0 < chunk; k0 += 16) {  // 16 pixels per step, 8 per lane half
-        // this lane's 8 consecutive pixels: the first one's (n, oy, ox) by
-        // division, the others by stepping along the row
-        const long pb = p0 + k0 + 8 * q;
-        const long pc = pb < total ? pb : 0;
-        int n = (int)(pc / hwo);
-        const int rem = (int)(pc - (long)n * hwo);
-        int oy = rem / Wo, ox = rem - oy * Wo;
-        s16x8 a, b;
+    if constexpr (NCP > NCOL)  // the padding columns of the last tile stay zero
+        for (int i = tid; i < 16 * (NCP - NCOL); i += 256) xs[i / (NCP - NCOL)][NCOL + i % (NCP - NCOL)] = 0;
+    f32x16 acc[TPW];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const long p = pb + i;
-            short av = 0, bv = 0;
+    for (int u = 0; u < TPW; ++u) acc[u] = f32x16{};
+    float bs[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // threads < 64: slot tid / 4, channels 8 (tid % 4) ..
+    for (int k0 = 0; k0 < chunk; k0 += 16) {
+        __syncthreads();  // the previous step's operands have been read
+        if (tid < 64) {   // g: 16 pixels x 4 vectors of 8 channels
+            const int pi = tid >> 2, v = tid & 3;
+            const long p = p0 + k0 + pi;
+            s16x8 g = s16x8{0, 0, 0, 0, 0, 0, 0, 0};
             if (p < total && p < p0 + chunk) {
-                const size_t o = (size_t)p * 32 + i32;  // A[co = i32][k = p]
-                av = (bf2f(Y[o]) > 0.0f) ? (short)dY[o] : (short)0;
-                if (bias) bsum += bf2f((uint16_t)av);
-                if (cvalid) {
-                    const int iy = oy * S + dy, ix = ox * S + dx;
-                    if (iy >= 0 && iy < H && ix >= 0 && ix < W)
-                        bv = (short)X[(((size_t)n * H + iy) * W + ix) * CIN + ci];
-                }
+                const s16x8 d8 = *reinterpret_cast<const s16x8*>(dY + (size_t)p * 32 + 8 * v);
+                const s16x8 y8 = *reinterpret_cast<const s16x8*>(Y + (size_t)p * 32 + 8 * v);
+#pragma unroll
+                for (int c = 0; c < 8; ++c) g[c] = (bf2f((uint16_t)y8[c]) > 0.0f) ? d8[c] : (short)0;
             }
-            a[i] = av;
-            b[i] = bv;
-            if (++ox == Wo) {
-                ox = 0;
-                if (++oy == Ho) {
-                    oy = 0;
-                    ++n;
-                }
+#pragma unroll
+            for (int c = 0; c < 8; ++c) bs[c] += bf2f((uint16_t)g[c]);
+            *reinterpret_cast<s16x8*>(&gs[pi][8 * v]) = g;
+        }
+        {  // x: 16 pixels x 9 taps x XV vectors; this thread's pixel slot is tid % 16
+            const int pi = tid & 15;
+            const long p = p0 + k0 + pi;
+            const bool pin = p < total && p < p0 + chunk;
+            const long pc = pin ? p : 0;
+            const int n = (int)(pc / hwo);
+            const int rem = (int)(pc - (long)n * hwo);
+            const int oy = rem / Wo, ox = rem - oy * Wo;
+            for (int r = tid >> 4; r < 9 * XV; r += 16) {
+                const int t = r / XV, v = r % XV;
+                const int iy = oy * S + t / 3 - 1, ix = ox * S + t % 3 - 1;
+                s16x8 x = s16x8{0, 0, 0, 0, 0, 0, 0, 0};
+                if (pin && iy >= 0 && iy < H && ix >= 0 && ix < W)
+                    x = *reinterpret_cast<const s16x8*>(X + (((size_t)n * H + iy) * W + ix) * CIN + 8 * v);
+                *reinterpret_cast<s16x8*>(&xs[pi][t * CIN + 8 * v]) = x;
             }
         }
-        acc = mfma16(a, b, acc);
+        __syncthreads();
+        s16x8 a;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a[i] = (short)gs[8 * q + i][i32];  // A[co = i32][pixel 8 q + i]
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+            const int tile = wave + 4 * u;
+            if (tile < NT) {  // uniform
+                s16x8 b;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) b[i] = (short)xs[8 * q + i][tile * 32 + i32];  // B[pixel][col]
+                acc[u] = mfma16(a, b, acc[u]);
+            }
+        }
     }
-    if (bias) {
-        const float other = __shfl_xor(bsum, 32);
-        if (q == 0) bpartial[(size_t)blockIdx.x * 32 + i32] = bsum + other;
+    if (tid < 64) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) bred[tid][c] = bs[c];
+    }
+    __syncthreads();
+    if (tid < 32) {
+        float sum = 0.0f;
+        for (int pi = 0; pi < 16; ++pi) sum += bred[pi * 4 + tid / 8][tid % 8];
+        bpartial[(size_t)blockIdx.x * 32 + tid] = sum;
     }
     float* out = partial + (size_t)blockIdx.x * 32 * NCOL;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const int co = 8 * (j / 4) + 4 * q + (j % 4);
-        if (cvalid) out[(size_t)co * NCOL + col] = acc[j];
+    for (int u = 0; u < TPW; ++u) {
+        const int col = (wave + 4 * u) * 32 + i32;
+        if (wave + 4 * u < NT && col < NCOL) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int co = 8 * (r / 4) + 4 * q + (r % 4);
+                out[(size_t)co * NCOL + col] = acc[u][r];
+            }
+        }
     }
 }
 
@@ -831,16 +866,16 @@ hipError_t cnn_layer_backward(hipStream_t st, int cin, int stride, const uint16_
     const int chunk = kWgradChunk;
     const int n_chunks = (int)((total + chunk - 1) / chunk);
     const int ncol = 9 * cin;
-    const dim3 wg(n_chunks, (ncol + 31) / 32);
+    const dim3 wg(n_chunks);
     float* bpart = partial + (size_t)n_chunks * 32 * ncol;
     if (cin == 8 && stride == 2)
-        hipLaunchKernelGGL((k_conv_wgrad<8, 2>), wg, dim3(64), 0, st, dY, Y, X, partial, bpart, N, H, W, Ho, Wo,
+        hipLaunchKernelGGL((k_conv_wgrad<8, 2>), wg, dim3(256), 0, st, dY, Y, X, partial, bpart, N, H, W, Ho, Wo,
                            chunk);
     else if (cin == 32 && stride == 2)
-        hipLaunchKernelGGL((k_conv_wgrad<32, 2>), wg, dim3(64), 0, st, dY, Y, X, partial, bpart, N, H, W, Ho, Wo,
+        hipLaunchKernelGGL((k_conv_wgrad<32, 2>), wg, dim3(256), 0, st, dY, Y, X, partial, bpart, N, H, W, Ho, Wo,
                            chunk);
     else if (cin == 32 && stride == 1)
-        hipLaunchKernelGGL((k_conv_wgrad<32, 1>), wg, dim3(64), 0, st, dY, Y, X, partial, bpart, N, H, W, Ho, Wo,
+        hipLaunchKernelGGL((k_conv_wgrad<32, 1>), wg, dim3(256), 0, st, dY, Y, X, partial, bpart, N, H, W, Ho, Wo,
                            chunk);
     else
         return hipErrorInvalidValue;
