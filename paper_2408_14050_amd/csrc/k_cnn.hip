@@ -669,7 +669,8 @@ __global__ __launch_bounds__(256) void k_reduce_groups(float* __restrict__ parti
     const int c0 = (int)blockIdx.y * kReduceGroup;
     const int c1 = c0 + kReduceGroup < n_chunks ? c0 + kReduceGroup : n_chunks;
     float s = 0.0f;
-    for (int c = c0; c < c1; ++c) s += partial[(size_t)c * n_out + k];
+#pragma unroll 8
+    for (int c = c0; c < c1; ++c) s += partial[(size_t)c * n_out + k];  // loads in flight together, sums in order
     partial[(size_t)c0 * n_out + k] = s;
 }
 
@@ -680,6 +681,7 @@ __global__ __launch_bounds__(256) void k_reduce_chunks(const float* __restrict__
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_out) return;
     float s = 0.0f;
+#pragma unroll 8
     for (int c = 0; c < n_chunks; c += step) s += partial[(size_t)c * n_out + k];
     out[k] = s;
 }
