@@ -33,7 +33,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // Pixels per weight-gradient partial (one block of k_conv_wgrad).
-constexpr int kWgradChunk = 512;
+constexpr int kWgradChunk = 256;
 
 // D += A B on v_mfma_f32_32x32x16_bf16 (lane layout in the header comment)
 __device__ __forceinline__ f32x16 mfma16(s16x8 a, s16x8 b, f32x16 c) {
