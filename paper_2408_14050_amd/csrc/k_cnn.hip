@@ -32,8 +32,10 @@ typedef short s16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// Pixels per weight-gradient partial (one block of k_conv_wgrad).
+// Pixels per weight-gradient partial (one block of k_conv_wgrad), and per
+// partial of the last layer's (one block of k_wgrad_last).
 constexpr int kWgradChunk = 256;
+constexpr int kLastChunk = 32;
 
 // D += A B on v_mfma_f32_32x32x16_bf16 (lane layout in the header comment)
 __device__ __forceinline__ f32x16 mfma16(s16x8 a, s16x8 b, f32x16 c) {
@@ -483,17 +485,28 @@ __global__ __launch_bounds__(320) void k_wgrad_last(const float* __restrict__ dZ
     const long p1 = p0 + chunk < total ? p0 + chunk : total;
     float acc = 0.0f;
     const int t = k / 32, ci = k % 32;
+    const int dy = t / 3 - 1, dx = t % 3 - 1;
+    // the chunk's first pixel by division, the others by stepping along the row
+    const long hw = (long)H * W;
+    int n = (int)(p0 / hw);
+    const int rem = (int)(p0 - (long)n * hw);
+    int y = rem / W, x = rem - y * W;
     for (long p = p0; p < p1; ++p) {
         const float g = dZ[p];
         if (k == 288) {
             acc += g;
-            continue;
+        } else {
+            const int iy = y + dy, ix = x + dx;
+            if (iy >= 0 && iy < H && ix >= 0 && ix < W)
+                acc += g * bf2f(X[(((size_t)n * H + iy) * W + ix) * 32 + ci]);
         }
-        const int n = (int)(p / ((long)H * W));
-        const int rem = (int)(p % ((long)H * W));
-        const int iy = rem / W + t / 3 - 1, ix = rem % W + t % 3 - 1;
-        if (iy < 0 || iy >= H || ix < 0 || ix >= W) continue;
-        acc += g * bf2f(X[(((size_t)n * H + iy) * W + ix) * 32 + ci]);
+        if (++x == W) {
+            x = 0;
+            if (++y == H) {
+                y = 0;
+                ++n;
+            }
+        }
     }
     partial[(size_t)blockIdx.x * 289 + k] = acc;
 }
@@ -844,7 +857,7 @@ hipError_t cnn_bce(hipStream_t st, const float* Z, const float* T, float* dZ, do
 hipError_t cnn_last_backward(hipStream_t st, const float* dZ, const uint16_t* X, const uint16_t* Wt,
                              uint16_t* dX, float* partial, float* gw_out, int N, int H, int W) {
     const long total = (long)N * H * W;
-    const int chunk = 256;
+    const int chunk = kLastChunk;
     const int n_chunks = (int)((total + chunk - 1) / chunk);
     hipLaunchKernelGGL(k_wgrad_last, dim3(n_chunks), dim3(320), 0, st, dZ, X, partial, N, H, W, chunk);
     reduce_chunks(st, partial, gw_out, n_chunks, 289);
@@ -852,6 +865,8 @@ hipError_t cnn_last_backward(hipStream_t st, const float* dZ, const uint16_t* X,
                        dX, N, H, W);
     return hipGetLastError();
 }
+
+size_t cnn_last_partial_floats(long pixels) { return (size_t)((pixels + kLastChunk - 1) / kLastChunk) * 289; }
 
 size_t cnn_wgrad_partial_floats(long pixels, int cin) {
     const int chunk = kWgradChunk;

@@ -37,6 +37,7 @@ hipError_t cnn_bce(hipStream_t st, const float* Z, const float* T, float* dZ, do
 hipError_t cnn_last_backward(hipStream_t st, const float* dZ, const uint16_t* X, const uint16_t* Wt,
                              uint16_t* dX, float* partial, float* gw_out, int N, int H, int W);
 size_t cnn_wgrad_partial_floats(long pixels, int cin);
+size_t cnn_last_partial_floats(long pixels);  // partials of cnn_last_backward over `pixels` logits
 hipError_t cnn_layer_backward(hipStream_t st, int cin, int stride, const uint16_t* dY,
                               const uint16_t* Y, const uint16_t* X, const uint16_t* Wt,
                               uint16_t* WT, uint16_t* dX, float* partial, float* gw_out, int N, int H,

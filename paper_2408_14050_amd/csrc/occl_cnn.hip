@@ -133,7 +133,7 @@ occl_status occl_ctx::cnn_backward(const uint16_t* X, int N, int H, int W, const
     size_t pmax = 0;
     for (int l = 0; l < kCnnLayers - 1; ++l)
         pmax = std::max(pmax, cnn_wgrad_partial_floats((long)N * Hs[l + 1] * Ws[l + 1], kLayers[l].cin));
-    pmax = std::max(pmax, (size_t)((ntile + 255) / 256) * 289);
+    pmax = std::max(pmax, cnn_last_partial_floats(ntile));
     const int nb = 256;
     occl_status s = ensure("cnn_z", ntile * sizeof(float), &z);
     if (s == OCCL_OK) s = ensure("cnn_dz", ntile * sizeof(float), &dz);
