@@ -168,7 +168,10 @@ def layer_slices():
     return out
 
 
-@pytest.mark.parametrize("shape", [(2, 64, 80), (1, 100, 36)])
+# (9, 256, 256): more than 64 weight-gradient partials in layers 0 and 1 and in
+# the last layer (576, 144 and 72), so both levels of the ordered partial sums
+# run, with a partly filled last group in layer 1 and the last layer
+@pytest.mark.parametrize("shape", [(2, 64, 80), (1, 100, 36), (9, 256, 256)])
 def test_backward_matches_oracle(gctx, torch, shape):
     N, H, W = shape
     rng = np.random.default_rng(7 + H)
@@ -189,12 +192,14 @@ def test_backward_matches_oracle(gctx, torch, shape):
         assert float(a @ b) >= 0.9999 * np.linalg.norm(a) * nrm - 1e-12, li
 
 
-def test_backward_is_deterministic(gctx, torch):
+@pytest.mark.parametrize("shape", [(2, 48, 64), (9, 256, 256)])
+def test_backward_is_deterministic(gctx, torch, shape):
+    N, H, W = shape
     rng = np.random.default_rng(11)
     theta = rand_theta(rng)
     gctx.occl_cnn_set_state(theta)
-    X = to_dev(torch, rand_input(rng, 2, 48, 64))
-    T = to_dev(torch, rng.uniform(size=(2, 3, 4)).astype(np.float32))
+    X = to_dev(torch, rand_input(rng, N, H, W))
+    T = to_dev(torch, rng.uniform(size=(N, -(-H // 16), -(-W // 16))).astype(np.float32))
     l1, g1 = gctx.occl_cnn_backward(X, T)
     l2, g2 = gctx.occl_cnn_backward(X, T)
     assert l1 == l2
