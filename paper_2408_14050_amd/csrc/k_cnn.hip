@@ -546,6 +546,9 @@ __global__ __launch_bounds__(256) void k_conv_dgrad(const uint16_t* __restrict__
         const int ny = iy + 1 - t / 3, nx = ix + 1 - t % 3;  // = oy * S, ox * S
         const int oy = ny / S, ox = nx / S;
         const bool ok = pv && ny >= 0 && nx >= 0 && (ny % S) == 0 && (nx % S) == 0 && oy < Ho && ox < Wo;
+        // a tap under which no pixel of the wavefront has an output adds
+        // nothing (with stride 2, 3 or 6 of the 9 taps of a row's pixels)
+        if (__ballot(ok) == 0) continue;  // uniform
         const size_t o = (((size_t)n * Ho + (ok ? oy : 0)) * Wo + (ok ? ox : 0)) * 32;
         const uint16_t* wrow = WT + ((size_t)t * 32 + i32) * 32;
 #pragma unroll
