@@ -35,6 +35,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 // Pixels per weight-gradient partial (one block of k_conv_wgrad), and per
 // partial of the last layer's (one block of k_wgrad_last).
 constexpr int kWgradChunk = 256;
+constexpr int kWgradStep = 32;  // pixels staged per step of k_conv_wgrad (a multiple of 16 dividing kWgradChunk)
 constexpr int kLastChunk = 32;
 
 // D += A B on v_mfma_f32_32x32x16_bf16 (lane layout in the header comment)
@@ -568,14 +569,15 @@ __global__ __launch_bounds__(256) void k_conv_dgrad(const uint16_t* __restrict__
 
 // wgrad partials of a 32-output-channel layer: block `chunk` computes every
 // 32 x 32 tile of dW[co][t*CIN + ci] (co rows, columns col = t*CIN + ci) over
-// the chunk's pixels; partial layout [chunk][32][9*CIN].  Per step of 16
-// pixels the block stages, with 16-byte loads, the relu-masked output
-// gradient g = dY [Y > 0] (gs[pixel][co]) and the input under each tap
+// the chunk's pixels; partial layout [chunk][32][9*CIN].  Per step of
+// kWgradStep pixels the block stages, with 16-byte loads, the relu-masked
+// output gradient g = dY [Y > 0] (gs[pixel][co]) and the input under each tap
 // (xs[pixel][col], zero outside the image) in LDS; wavefront w then runs the
-// column tiles w, w + 4, ..., taking its MFMA operands from LDS (8 pixels of
-// one row or column per lane half).  It also writes the bias gradient's
-// partials, bpartial [chunk][32]: the sum of g over the chunk's pixels, per
-// pixel slot in step order, then the 16 slots in order.
+// column tiles w, w + 4, ..., one MFMA per 16 pixels in pixel order, taking
+// its operands from LDS (8 pixels of one row or column per lane half).  It
+// also writes the bias gradient's partials, bpartial [chunk][32]: the sum of
+// g over the chunk's pixels, per pixel slot in step order, then the slots in
+// order.
 template <int CIN, int S>
 __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t* __restrict__ dY,
                                                     const uint16_t* __restrict__ Y,
@@ -587,23 +589,24 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t* __restrict__
     constexpr int NCP = NT * 32;          // columns, padded to whole tiles
     constexpr int TPW = (NT + 3) / 4;     // tiles per wavefront
     constexpr int XV = CIN / 8;           // 16-byte vectors of X per pixel
-    __shared__ __align__(16) uint16_t gs[16][32];
-    __shared__ __align__(16) uint16_t xs[16][NCP];
-    __shared__ float bred[64][8];
+    constexpr int KS = kWgradStep;        // pixels per staged step (two MFMA K blocks of 16)
+    __shared__ __align__(16) uint16_t gs[KS][32];
+    __shared__ __align__(16) uint16_t xs[KS][NCP];
+    __shared__ float bred[4 * KS][8];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int q = lane >> 5, i32 = lane & 31;
     const long total = (long)N * Ho * Wo;
     const long p0 = (long)blockIdx.x * chunk;
     const long hwo = (long)Ho * Wo;
     if constexpr (NCP > NCOL)  // the padding columns of the last tile stay zero
-        for (int i = tid; i < 16 * (NCP - NCOL); i += 256) xs[i / (NCP - NCOL)][NCOL + i % (NCP - NCOL)] = 0;
+        for (int i = tid; i < KS * (NCP - NCOL); i += 256) xs[i / (NCP - NCOL)][NCOL + i % (NCP - NCOL)] = 0;
     f32x16 acc[TPW];
 #pragma unroll
     for (int u = 0; u < TPW; ++u) acc[u] = f32x16{};
-    float bs[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // threads < 64: slot tid / 4, channels 8 (tid % 4) ..
-    for (int k0 = 0; k0 < chunk; k0 += 16) {
-        __syncthreads();  // the previous step's operands have been read
-        if (tid < 64) {   // g: 16 pixels x 4 vectors of 8 channels
+    float bs[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // threads < 4 KS: slot tid / 4, channels 8 (tid % 4) ..
+    for (int k0 = 0; k0 < chunk; k0 += KS) {
+        __syncthreads();    // the previous step's operands have been read
+        if (tid < 4 * KS) {  // g: KS pixels x 4 vectors of 8 channels
             const int pi = tid >> 2, v = tid & 3;
             const long p = p0 + k0 + pi;
             s16x8 g = s16x8{0, 0, 0, 0, 0, 0, 0, 0};
@@ -617,15 +620,15 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t* __restrict__
             for (int c = 0; c < 8; ++c) bs[c] += bf2f((uint16_t)g[c]);
             *reinterpret_cast<s16x8*>(&gs[pi][8 * v]) = g;
         }
-        {  // x: 16 pixels x 9 taps x XV vectors; this thread's pixel slot is tid % 16
-            const int pi = tid & 15;
+        {  // x: KS pixels x 9 taps x XV vectors; this thread's pixel slot is tid % KS
+            const int pi = tid % KS;
             const long p = p0 + k0 + pi;
             const bool pin = p < total && p < p0 + chunk;
             const long pc = pin ? p : 0;
             const int n = (int)(pc / hwo);
             const int rem = (int)(pc - (long)n * hwo);
             const int oy = rem / Wo, ox = rem - oy * Wo;
-            for (int r = tid >> 4; r < 9 * XV; r += 16) {
+            for (int r = tid / KS; r < 9 * XV; r += 256 / KS) {
                 const int t = r / XV, v = r % XV;
                 const int iy = oy * S + t / 3 - 1, ix = ox * S + t % 3 - 1;
                 s16x8 x = s16x8{0, 0, 0, 0, 0, 0, 0, 0};
@@ -635,28 +638,31 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t* __restrict__
             }
         }
         __syncthreads();
-        s16x8 a;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) a[i] = (short)gs[8 * q + i][i32];  // A[co = i32][pixel 8 q + i]
+        for (int h = 0; h < KS; h += 16) {  // pixels in order: the same MFMA sequence as 16-pixel steps
+            s16x8 a;
 #pragma unroll
-        for (int u = 0; u < TPW; ++u) {
-            const int tile = wave + 4 * u;
-            if (tile < NT) {  // uniform
-                s16x8 b;
+            for (int i = 0; i < 8; ++i) a[i] = (short)gs[h + 8 * q + i][i32];  // A[co = i32][pixel]
 #pragma unroll
-                for (int i = 0; i < 8; ++i) b[i] = (short)xs[8 * q + i][tile * 32 + i32];  // B[pixel][col]
-                acc[u] = mfma16(a, b, acc[u]);
+            for (int u = 0; u < TPW; ++u) {
+                const int tile = wave + 4 * u;
+                if (tile < NT) {  // uniform
+                    s16x8 b;
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) b[i] = (short)xs[h + 8 * q + i][tile * 32 + i32];  // B[pixel][col]
+                    acc[u] = mfma16(a, b, acc[u]);
+                }
             }
         }
     }
-    if (tid < 64) {
+    if (tid < 4 * KS) {
 #pragma unroll
         for (int c = 0; c < 8; ++c) bred[tid][c] = bs[c];
     }
     __syncthreads();
     if (tid < 32) {
         float sum = 0.0f;
-        for (int pi = 0; pi < 16; ++pi) sum += bred[pi * 4 + tid / 8][tid % 8];
+        for (int pi = 0; pi < KS; ++pi) sum += bred[pi * 4 + tid / 8][tid % 8];
         bpartial[(size_t)blockIdx.x * 32 + tid] = sum;
     }
     float* out = partial + (size_t)blockIdx.x * 32 * NCOL;
