@@ -569,22 +569,23 @@ __global__ __launch_bounds__(256) void k_conv_dgrad(const uint16_t* __restrict__
 
 // wgrad partials of a 32-output-channel layer: block `chunk` computes every
 // 32 x 32 tile of dW[co][t*CIN + ci] (co rows, columns col = t*CIN + ci) over
-// the chunk's pixels; partial layout [chunk][32][9*CIN].  Per step of
+// the chunk's pixels; partial layout [chunk][32 * 9*CIN + 32]: dW, then the
+// bias gradient's 32 (the layout of the layer's gradient).  Per step of
 // kWgradStep pixels the block stages, with 16-byte loads, the relu-masked
 // output gradient g = dY [Y > 0] (gs[pixel][co]) and the input under each tap
 // (xs[pixel][col], zero outside the image) in LDS; wavefront w then runs the
 // column tiles w, w + 4, ..., one MFMA per 16 pixels in pixel order, taking
-// its operands from LDS (8 pixels of one row or column per lane half).  It
-// also writes the bias gradient's partials, bpartial [chunk][32]: the sum of
-// g over the chunk's pixels, per pixel slot in step order, then the slots in
-// order.
+// its operands from LDS (8 pixels of one row or column per lane half).  The
+// bias gradient's partial is the sum of g over the chunk's pixels, per pixel
+// slot in step order, then the slots in order.
 template <int CIN, int S>
 __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t* __restrict__ dY,
                                                     const uint16_t* __restrict__ Y,
                                                     const uint16_t* __restrict__ X,
-                                                    float* __restrict__ partial, float* __restrict__ bpartial,
-                                                    int N, int H, int W, int Ho, int Wo, int chunk) {
+                                                    float* __restrict__ partial, int N, int H, int W, int Ho,
+                                                    int Wo, int chunk) {
     constexpr int NCOL = 9 * CIN;
+    constexpr int NOUT = 32 * NCOL + 32;  // partial row: dW, then the bias
     constexpr int NT = (NCOL + 31) / 32;  // column tiles
     constexpr int NCP = NT * 32;          // columns, padded to whole tiles
     constexpr int TPW = (NT + 3) / 4;     // tiles per wavefront
@@ -663,9 +664,9 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t* __restrict__
     if (tid < 32) {
         float sum = 0.0f;
         for (int pi = 0; pi < KS; ++pi) sum += bred[pi * 4 + tid / 8][tid % 8];
-        bpartial[(size_t)blockIdx.x * 32 + tid] = sum;
+        partial[(size_t)blockIdx.x * NOUT + 32 * NCOL + tid] = sum;
     }
-    float* out = partial + (size_t)blockIdx.x * 32 * NCOL;
+    float* out = partial + (size_t)blockIdx.x * NOUT;
 #pragma unroll
     for (int u = 0; u < TPW; ++u) {
         const int col = (wave + 4 * u) * 32 + i32;
@@ -893,20 +894,15 @@ hipError_t cnn_layer_backward(hipStream_t st, int cin, int stride, const uint16_
     const int n_chunks = (int)((total + chunk - 1) / chunk);
     const int ncol = 9 * cin;
     const dim3 wg(n_chunks);
-    float* bpart = partial + (size_t)n_chunks * 32 * ncol;
     if (cin == 8 && stride == 2)
-        hipLaunchKernelGGL((k_conv_wgrad<8, 2>), wg, dim3(256), 0, st, dY, Y, X, partial, bpart, N, H, W, Ho, Wo,
-                           chunk);
+        hipLaunchKernelGGL((k_conv_wgrad<8, 2>), wg, dim3(256), 0, st, dY, Y, X, partial, N, H, W, Ho, Wo, chunk);
     else if (cin == 32 && stride == 2)
-        hipLaunchKernelGGL((k_conv_wgrad<32, 2>), wg, dim3(256), 0, st, dY, Y, X, partial, bpart, N, H, W, Ho, Wo,
-                           chunk);
+        hipLaunchKernelGGL((k_conv_wgrad<32, 2>), wg, dim3(256), 0, st, dY, Y, X, partial, N, H, W, Ho, Wo, chunk);
     else if (cin == 32 && stride == 1)
-        hipLaunchKernelGGL((k_conv_wgrad<32, 1>), wg, dim3(256), 0, st, dY, Y, X, partial, bpart, N, H, W, Ho, Wo,
-                           chunk);
+        hipLaunchKernelGGL((k_conv_wgrad<32, 1>), wg, dim3(256), 0, st, dY, Y, X, partial, N, H, W, Ho, Wo, chunk);
     else
         return hipErrorInvalidValue;
-    reduce_chunks(st, partial, gw_out, n_chunks, 32 * ncol);
-    reduce_chunks(st, bpart, gw_out + 32 * ncol, n_chunks, 32);
+    reduce_chunks(st, partial, gw_out, n_chunks, 32 * ncol + 32);  // dW and db in one pass
     if (dX) {  // input gradient (not needed for the first layer)
         if (cin != 32) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_transpose_w, dim3((32 * 9 * 32 + 255) / 256), dim3(256), 0, st, Wt, WT);
