@@ -362,7 +362,43 @@ def profiles_from(run_dir: str, workload: str) -> int:
                 f.write("\n".join(lines) + "\n")
     with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
         json.dump(traffic, f, indent=1)
+    write_profile_index()
     print(json.dumps(traffic, indent=1))
+    return 0
+
+
+def write_profile_index() -> int:
+    """profiles/INDEX.md: one line per summary of profiles/traffic.json
+    (workload, kernel, average duration, HBM bytes per dispatch, file), and
+    the other summaries in profiles/."""
+    import glob
+    with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
+        traffic = json.load(f)
+    rows, listed = [], set()
+    for key, e in traffic.items():
+        if not isinstance(e, dict) or "workload" not in e:
+            continue
+        k = key.split(" @ ")[0]
+        tag = e["workload"].split(":")[0].replace(" ", "_").replace("x8_views", "v8")
+        name = k.replace("<", "_").replace(">", "").replace(", ", "_").replace(",", "_") + f"__{tag}.txt"
+        if not os.path.exists(os.path.join(ROOT, "profiles", name)):
+            continue
+        listed.add(name)
+        rows.append((e["workload"], k, e["avg_us"], e["read_bytes"] / 1e6, e["write_bytes"] / 1e6, name))
+    lines = ["# rocprofv3 summaries", "",
+             "One file per kernel and workload, written by `python bench.py --profiles-from gpurun_out` from the",
+             "trace and counter runs whose commands each file lists. Durations are the trace's average per dispatch;",
+             "HBM bytes are the FETCH_SIZE and WRITE_SIZE counters per dispatch, scaled by what the same counters",
+             "read for a plain copy of known size (`traffic.json` holds the figures and the source hash of each).", "",
+             "| workload | kernel | avg µs | HBM read MB | HBM write MB | file |", "|---|---|---|---|---|---|"]
+    for wl, k, us, rd, wr, name in sorted(rows):
+        lines.append(f"| {wl} | `{k}` | {us:.1f} | {rd:.1f} | {wr:.1f} | [{name}]({name}) |")
+    other = sorted(os.path.basename(x) for x in glob.glob(os.path.join(ROOT, "profiles", "*.txt"))
+                   if os.path.basename(x) not in listed)
+    if other:
+        lines += ["", "Other summaries:", ""] + [f"- [{x}]({x})" for x in other]
+    with open(os.path.join(ROOT, "profiles", "INDEX.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
     return 0
 
 
@@ -871,6 +907,7 @@ def main() -> int:
     ap.add_argument("--no-c2", action="store_true")
     ap.add_argument("--c2-only", action="store_true", help="only the 3840x2160 x15 section")
     ap.add_argument("--profiles-from", default=None, metavar="DIR")
+    ap.add_argument("--profiles-index", action="store_true", help="only rewrite profiles/INDEX.md")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-only", action="store_true", help="only the learned-path section")
     ap.add_argument("--train-only", action="store_true", help="only the network's training step")
@@ -890,6 +927,8 @@ def main() -> int:
         return copy_probe(args.copy_probe)
     if args.profiles_from:
         return profiles_from(args.profiles_from, C1_WORKLOAD)
+    if args.profiles_index:
+        return write_profile_index()
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the detector's "
