@@ -457,6 +457,24 @@ __device__ __forceinline__ void bitonic_sort(uint64_t (&key)[K], int lane) {
     }
 }
 
+// Ascending sort of the 64*K keys of key[]: the bitonic network for a power
+// of two K, else over the next power of two with the added slots holding
+// ~0 (above every key), so the sorted keys fill slots 0 .. K - 1 again.
+template <int K>
+__device__ __forceinline__ void sort_keys(uint64_t (&key)[K], int lane) {
+    if constexpr ((K & (K - 1)) == 0) {
+        bitonic_sort<K>(key, lane);
+    } else {
+        constexpr int KP = K < 4 ? 4 : (K < 8 ? 8 : 16);
+        uint64_t kp[KP];
+#pragma unroll
+        for (int k = 0; k < KP; ++k) kp[k] = k < K ? key[k] : ~0ull;
+        bitonic_sort<KP>(kp, lane);
+#pragma unroll
+        for (int k = 0; k < K; ++k) key[k] = kp[k];
+    }
+}
+
 struct WaveLds {
     float2* WVin;   // (W, V) by offset index e (W NaN where the sample is dropped)
     uint32_t* Oin;  // f2ord(W) by e (the search keys of the co-rank merge)
@@ -469,7 +487,7 @@ constexpr int kMaxRunsCap = 16;
 // Largest number of monotone runs for which the co-rank path is used
 // (above it the full sort is cheaper).
 template <int K>
-constexpr int max_runs() { return K == 1 ? 4 : K == 2 ? 5 : K == 4 ? 6 : K == 8 ? 8 : 12; }
+constexpr int max_runs() { return K == 1 ? 4 : K == 2 ? 5 : K <= 4 ? 6 : K <= 8 ? 8 : 12; }
 
 // (W, e) ordering of two samples: a before b
 __device__ __forceinline__ bool key_less(float wa, int ea, float wb, int eb) {
@@ -665,7 +683,7 @@ __device__ __forceinline__ void order_test_lds(uint8_t* __restrict__ Mv, int W, 
         // The searches of up to KC samples of a lane advance in lockstep, so
         // their dependent LDS reads overlap instead of queueing one after
         // the other.
-        constexpr int KC = K < 4 ? K : 4;
+        constexpr int KC = K < 4 ? K : (K % 4 == 0 ? 4 : 3);  // divides K (K = 6: 3)
 #pragma unroll
         for (int k0 = 0; k0 < K; k0 += KC) {
             for (int i = 0; i + 1 < R; ++i) {
@@ -714,7 +732,7 @@ __device__ __forceinline__ void order_test_lds(uint8_t* __restrict__ Mv, int W, 
             const uint32_t e = (uint32_t)(k * 64 + lane);
             key[k] = kept[k] ? (((uint64_t)f2ord(wk[k]) << 32) | e) : ~0ull;
         }
-        bitonic_sort<K>(key, lane);
+        sort_keys<K>(key, lane);
         // the sorted array holds the origin of position p in key[k]; scatter the
         // inverse (origin -> position) into the key array, unused on this
         // path, so the test below runs per kept sample.  Every read of WVin
@@ -953,10 +971,13 @@ constexpr int waves_per_block() { return KMAX >= 16 ? 2 : 4; }
 // held to the hardware's 8 wavefronts per SIMD: the compiler then keeps to 96
 // scalar registers, spilling a few more into VGPR lanes.  The pass is bound
 // by chains of dependent loads (gather, LDS exchanges, merge searches), so
-// the extra wavefronts pay: c1 scanline pass 31.0 -> 26.6 us.  The longer
-// forms are limited by LDS below 8 anyway.
+// the extra wavefronts pay: c1 scanline pass 31.0 -> 26.6 us.  The K = 4 and
+// K = 8 forms are held to the 6 and 4 wavefronts per SIMD they reached before
+// their three-quarter forms (K = 3, 6) were added, which would otherwise cost
+// each a wavefront (80 -> 90 and 128 -> 136 VGPRs; the K = 8 form now spills
+// 8 bytes per lane to scratch): 3840x2160 x15 scanline pass 1.91 -> 1.88 ms.
 template <int KMAX>
-constexpr int min_waves_per_simd() { return KMAX <= 2 ? 8 : 1; }
+constexpr int min_waves_per_simd() { return KMAX <= 2 ? 8 : KMAX == 4 ? 6 : KMAX == 8 ? 4 : 1; }
 
 // (W, V) pair arrays per wavefront in LDS: the inputs WVin and the sorted
 // WVs.  The long-scanline forms are limited by LDS, so their sorted array
@@ -1004,6 +1025,14 @@ __device__ __forceinline__ void scan_item(const FrameDesc& f, int v, uint32_t pi
             scanline<1, G>(f.D, H, W, Mv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, n, th, L, lane);
         else
             scanline<2, G>(f.D, H, W, Mv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, n, th, L, lane);
+    } else if constexpr ((KMAX == 4 || KMAX == 8) && G == 0) {
+        // three quarters of the class's slots when they hold the scanline
+        // (the class's registers are sized for KMAX either way)
+        constexpr int K3 = KMAX * 3 / 4;
+        if (n <= 64 * K3)
+            scanline<K3, 0>(f.D, H, W, Mv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, n, th, L, lane);
+        else
+            scanline<KMAX, 0>(f.D, H, W, Mv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, n, th, L, lane);
     } else {
         scanline<KMAX, G>(f.D, H, W, Mv, cx, cy, vt.c[v], vt.s[v], vt.r[v], h, n, th, L, lane);
     }
