@@ -168,6 +168,25 @@ def test_scan_length_classes(gctx, torch, ref, L):
     assert_parity(M, M_ref, None, f"L={L}")
 
 
+def test_long_scanline_forms_many_runs(gctx, torch, ref):
+    """The long-scanline classes' three-quarter forms (K = 3 for 129..192
+    samples, K = 6 for 257..384) and the full forms at their boundaries, on
+    a block pattern that cuts every scanline into many monotone runs
+    (a disparity step of 20 every 5 to 7 pixels: about n / 6 runs), so the
+    padded bitonic route of the ordering runs as well as the co-rank merge."""
+    H, W = 420, 440
+    y, x = np.mgrid[0:H, 0:W]
+    D = (20.0 * (((x // 5) + (y // 7)) % 2) + 0.01 * x + 0.02 * y).astype(np.float32)
+    angles = np.array([0.0, 90.0, 45.0, 180.0, 27.5, 0.0, 270.0, 135.0, 0.0])
+    ratios = np.ones(len(angles), np.float32)
+    L = np.array([128, 150, 191, 192, 256, 300, 383, 384, 511])  # n = L + 1 (even L) or L
+    M_ref, T, nc_ref = ref.detect(D, angles, ratios, L, want_tight=True)
+    M, nc = run_gpu(gctx, torch, D, angles, ratios, L, counts=True)
+    np.testing.assert_array_equal(nc, nc_ref)
+    assert_parity(M, M_ref, T, "block pattern, long scanlines")
+    assert M_ref.sum() > 0
+
+
 @pytest.mark.parametrize("N", [1, 2, 3, 4, 7, 64])
 def test_neighbour_counts(gctx, torch, ref, N):
     sc = scenes.make_c1_like(78, W=256, H=160, n_objects=8)
